@@ -1,0 +1,126 @@
+"""Pins for the oracle's Philox-4x32-10 (definition: Salmon et al., SC'11).
+
+No known-answer vectors are available, so the generator is pinned by closed
+forms of one and two rounds, by an independent inversion of every round, and
+by statistics of the 10-round output.
+"""
+import numpy as np
+import pytest
+
+from oracle import philox
+
+MASK = 0xFFFFFFFF
+
+
+def _hilo(a, b):
+    p = (a * b) & ((1 << 64) - 1)
+    return p >> 32, p & MASK
+
+
+def _words(out):
+    return tuple(int(np.asarray(w).reshape(-1)[0]) for w in out)
+
+
+def test_zero_rounds_is_identity():
+    ctr = (1, 2, 3, 0xFFFFFFFF)
+    assert _words(philox.philox4x32(ctr, (5, 6), rounds=0)) == ctr
+
+
+@pytest.mark.parametrize("x0", [1, 0x12345678, 0xFFFFFFFF])
+def test_one_round_first_word_goes_through_m0(x0):
+    # only x0 non-zero, zero key: the M0 product lands in words 2 (high) and 3 (low)
+    h0, l0 = _hilo(philox.M0, x0)
+    assert _words(philox.philox4x32((x0, 0, 0, 0), (0, 0), rounds=1)) == (0, 0, h0, l0)
+
+
+@pytest.mark.parametrize("x2", [1, 0x9ABCDEF0, 0xFFFFFFFF])
+def test_one_round_third_word_goes_through_m1(x2):
+    h1, l1 = _hilo(philox.M1, x2)
+    assert _words(philox.philox4x32((0, 0, x2, 0), (0, 0), rounds=1)) == (h1, l1, 0, 0)
+
+
+def test_one_round_key_and_passthrough_words():
+    # x1 and x3 are only xor-ed: x1 with k0 into word 0, x3 with k1 into word 2
+    out = _words(philox.philox4x32((0, 0xA5A5A5A5, 0, 0x0F0F0F0F), (0x11111111, 0x22222222), rounds=1))
+    assert out == (0xA5A5A5A5 ^ 0x11111111, 0, 0x0F0F0F0F ^ 0x22222222, 0)
+
+
+def test_two_rounds_use_bumped_key():
+    k0, k1 = 0x01234567, 0x89ABCDEF
+    # round 1 on a zero counter gives (k0, 0, k1, 0); round 2 multiplies those
+    h0, l0 = _hilo(philox.M0, k0)
+    h1, l1 = _hilo(philox.M1, k1)
+    k0b, k1b = (k0 + philox.W0) & MASK, (k1 + philox.W1) & MASK
+    want = (h1 ^ k0b, l1, h0 ^ k1b, l0)
+    assert _words(philox.philox4x32((0, 0, 0, 0), (k0, k1), rounds=2)) == want
+
+
+def _inverse_round(y, k0, k1):
+    # invert one round: the low product words give x0, x2 through the modular
+    # inverses of the (odd) multipliers; the high words then unmask x3 and x1
+    inv0 = pow(philox.M0, -1, 1 << 32)
+    inv1 = pow(philox.M1, -1, 1 << 32)
+    y0, y1, y2, y3 = y
+    x0 = (y3 * inv0) & MASK
+    x2 = (y1 * inv1) & MASK
+    h0 = (philox.M0 * x0) >> 32
+    h1 = (philox.M1 * x2) >> 32
+    return (x0, y0 ^ h1 ^ k0, x2, y2 ^ h0 ^ k1)
+
+
+@pytest.mark.parametrize("seed", [0, 7, 2**40 + 3])
+def test_ten_rounds_invert_to_counter(seed):
+    rng = np.random.default_rng(seed)
+    key = philox.seed_key(seed)
+    for _ in range(20):
+        ctr = tuple(int(v) for v in rng.integers(0, 1 << 32, 4, dtype=np.uint64))
+        y = _words(philox.philox4x32(ctr, key))
+        for r in range(philox.ROUNDS - 1, -1, -1):
+            k0 = (key[0] + r * philox.W0) & MASK
+            k1 = (key[1] + r * philox.W1) & MASK
+            y = _inverse_round(y, k0, k1)
+        assert y == ctr
+
+
+def _stream(n, seed=42):
+    g = np.arange(n, dtype=np.uint64)
+    return philox.philox4x32((g, np.zeros_like(g), np.zeros_like(g), np.zeros_like(g)),
+                             philox.seed_key(seed))
+
+
+def test_output_bits_balanced():
+    n = 1 << 16
+    for w in _stream(n):
+        bits = (w[:, None] >> np.arange(32, dtype=np.uint64)) & np.uint64(1)
+        frac = bits.mean(axis=0)
+        # binomial sigma = 0.5/sqrt(n) ~ 0.00195; allow 5 sigma
+        assert np.all(np.abs(frac - 0.5) < 5 * 0.5 / np.sqrt(n))
+
+
+def test_bytes_chi_square():
+    from scipy import stats
+    n = 1 << 16
+    words = np.concatenate([w for w in _stream(n)])
+    b = np.concatenate([(words >> np.uint64(8 * i)) & np.uint64(0xFF) for i in range(4)])
+    counts = np.bincount(b.astype(np.int64), minlength=256)
+    chi2, p = stats.chisquare(counts)
+    assert 1e-4 < p
+
+
+def test_avalanche_on_counter_bit():
+    n = 4096
+    g = np.arange(n, dtype=np.uint64) * np.uint64(977)
+    z = np.zeros_like(g)
+    key = philox.seed_key(99)
+    a = philox.philox4x32((g, z, z, z), key)
+    flips = []
+    for bit in (0, 13, 31):
+        b = philox.philox4x32((g ^ np.uint64(1 << bit), z, z, z), key)
+        diff = np.zeros(n, dtype=np.int64)
+        for wa, wb in zip(a, b):
+            x = wa ^ wb
+            diff += np.array([bin(int(v)).count("1") for v in x])
+        flips.append(diff.mean())
+    # 128 output bits: about half flip on average
+    for f in flips:
+        assert abs(f - 64.0) < 1.0
