@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Throughput of the initial-conditions path on one MI355X.
+
+One step = one gg_make_ic call: seeded white noise -> forward r2c 3D FFT ->
+Eq. (1)-(2) filter -> three c2r inverse FFTs -> Zel'dovich positions and
+velocities (arxiv 2511.10353, Sec. 2.1-2.2), with every input and output
+resident in HBM.  The default workload is the 1024^3 lattice in a
+2000 Mpc/h box with single-precision passes; the double-precision path is
+timed beside it.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "grid cells/s noise->ICs (FP32 vs FP64) at 1 GPU + FFT HBM GB/s % peak"
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = ["P1 noise+z-r2c", "P2 y-fwd", "P3 x-fwd+filter+x-inv", "P4 y-inv x3", "P5 z-c2r+zeldovich"]
+
+
+def pass_bytes(n, elem):
+    """Algorithmic HBM bytes of each fused pass (elem = bytes of one real).
+
+    A spectrum row holds k2 in [0, N/2), so one spectrum is N^3/2 complex
+    values = N^3 * elem bytes; positions and velocities are float32.
+    """
+    n3 = n ** 3
+    spec = n3 * elem
+    particles = 2 * 3 * n3 * 4
+    return [spec,                      # P1: write W~
+            2 * spec,                  # P2: read + write
+            spec + 2 * spec,           # P3: read W~, write F, G
+            2 * spec + 3 * spec,       # P4: read F, G, write A, B, C
+            3 * spec + particles]      # P5: read A, B, C, write pos, vel
+
+
+def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42):
+    plan = gg.Plan(n, box, gg.Cosmo(), dtype=dtype)
+    pos = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+    vel = torch.empty_like(pos)
+    work = plan.workspace()
+    for i in range(warmup):
+        plan.make_ic(seed + i, pos, vel, work=work)
+    torch.cuda.synchronize()
+    plan.timing_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(steps):
+        plan.make_ic(seed + i, pos, vel, work=work)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop) / steps
+    pass_ms, calls = plan.timing_read()
+    plan.timing_enable(False)
+    pass_avg = [t / max(calls, 1) for t in pass_ms]
+    elem = 4 if dtype == "f32" else 8
+    nbytes = pass_bytes(n, elem)
+    passes = []
+    for name, t, b in zip(PASS_NAMES, pass_avg, nbytes):
+        gbs = b / (t * 1e-3) / 1e9 if t > 0 else 0.0
+        passes.append({"pass": name, "ms": round(t, 4), "bytes": b, "GB/s": round(gbs, 1),
+                       "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+    del pos, vel, work, plan
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms, "wall_s": wall, "cells_per_s": n ** 3 / (ms * 1e-3), "passes": passes,
+            "bytes_per_step": sum(nbytes)}
+
+
+def cpu_baseline(n=256, box=500.0):
+    """The FP64 oracle, untuned, on the host cores: one full pipeline at n^3."""
+    import numpy as np  # noqa: F401
+    from oracle import cosmology, pipeline
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    pipeline.make_ic(n, box, cosmology.Cosmology(), 42, workers=cores)
+    dt = time.perf_counter() - t0
+    return {"value": round(n ** 3 / dt, 1), "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"full FP64 oracle pipeline (noise, rfftn, filter, 3 irfftn, particles) on one "
+                      f"{n}^3 lattice, box {box:g} Mpc/h, seed 42; scipy.fft workers={cores}; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--box", type=float, default=2000.0)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the path holds the whole lattice on a single device "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2511_10353_amd as gg
+
+    gg.lib()
+    f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup)
+    f64 = None
+    if not args.no_fp64:
+        f64 = time_path(gg, torch, args.n, args.box, "f64", args.fp64_steps, 1)
+    dom = max(f32["passes"], key=lambda p: p["ms"])
+    roofline = {"bound": "hbm", "kernel": dom["pass"], "achieved": dom["GB/s"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dom["frac_hbm"], "traffic": None}
+    out = {
+        "metric": METRIC,
+        "value": round(f32["cells_per_s"], 1),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded Philox-4x32-10 white noise, analytic BBKS spectrum",
+        "config": {"workload": f"{args.n}^3 lattice, box {args.box:g} Mpc/h, noise->ICs, FP32 passes "
+                               f"(FP64 noise, sigma8 integral and position sum)",
+                   "n": args.n, "box_mpc_h": args.box, "seed": 42, "sigma8": 0.8, "z_init": 100.0},
+        "hbm_GBs_step": round(f32["bytes_per_step"] / (f32["ms_per_step"] * 1e-3) / 1e9, 1),
+        "frac_hbm_step": round(f32["bytes_per_step"] / (f32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "passes": f32["passes"],
+        "roofline": roofline,
+    }
+    if f64 is not None:
+        out["fp64"] = {"value": round(f64["cells_per_s"], 1), "unit": "cells/s",
+                       "ms_per_step": round(f64["ms_per_step"], 4), "passes": f64["passes"],
+                       "fp32_speedup": round(f64["ms_per_step"] / f32["ms_per_step"], 3)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,175 @@
+/*
+ * gg.h - C ABI of the MI355X (gfx950) initial-conditions library.
+ *
+ * The library computes the data-parallel hot path of the Ginnungagap
+ * initial-conditions method (arxiv 2511.10353, Sec. 2.1-2.2) on one GPU that
+ * holds the whole N^3 lattice:
+ *
+ *   white noise W (Sec. 2, step 1)
+ *   -> forward real-to-complex 3D transform W~
+ *   -> Eq. (1)  delta~ = sqrt(P(k) N^3/L^3) W~   and
+ *      Eq. (2)  psi~_j = i k_j / k^2 delta~,  j = 0, 1, 2
+ *   -> three complex-to-real inverse transforms psi_j
+ *   -> Eq. (3)  Zel'dovich positions x_j = q_j + psi_j and velocities
+ *               v_j = a H(a) f psi_j at the lattice points q.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Lattice cell (m0, m1, m2), m_i in [0, N), has linear index
+ *   c = (m0 N + m1) N + m2: row-major, axis 2 contiguous.
+ * - Real field ("R"): N^3 values of the plan's dtype (float or double).
+ * - Half spectrum ("H"): N * N * (N/2 + 1) complex values, interleaved
+ *   (re, im) of the plan's dtype, mode (k0, k1, k2) at
+ *   (k0 N + k1) (N/2 + 1) + k2, k2 in [0, N/2]; the same layout as
+ *   numpy.fft.rfftn of the real field.
+ * - Forward transform unnormalised, exp(-2 pi i k.m/N); inverse normalised
+ *   by 1/N^3, exp(+2 pi i k.m/N).
+ * - Signed mode index s(k) = k for k < N/2, k - N above; k_j = 2 pi s_j / L.
+ *   The filter zeroes k = 0 and every mode with |s_j| = N/2 on any axis.
+ * - Particle arrays: float32, structure of arrays, component j of cell c at
+ *   j N^3 + c (3 N^3 values each for positions and velocities).
+ * - Noise: cell c belongs to Philox-4x32-10 group g = c/4 (key = seed,
+ *   counter = (g, stream_id, 0)); its four words give two Box-Muller pairs
+ *   evaluated in binary64 with a fixed operation sequence, so a cell's value
+ *   depends only on (seed, stream_id, c).  The float path stores the binary64
+ *   deviate rounded to nearest float.
+ *
+ * Memory, streams, errors
+ * -----------------------
+ * - Every data pointer is a device pointer owned by the caller; the library
+ *   never frees it.  Pointers must be 256-byte aligned.  Nothing on the hot
+ *   calls allocates memory.
+ * - ``stream`` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Every launch is asynchronous on that stream; a fault inside a kernel is
+ *   reported by the caller's next synchronisation, not by the call.
+ * - Arguments are validated before anything is launched: a bad argument
+ *   returns GG_ERR_INVALID_ARG and launches nothing.  gg_last_error() then
+ *   holds a message (per thread).  No call throws across the ABI.
+ * - A plan is read-only after gg_plan_create, except for the timing records
+ *   of gg_timing_enable; calls on one plan from several streams are safe when
+ *   each call has its own work buffer and timing is off.
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GG_OK = 0,
+    GG_ERR_INVALID_ARG = 1,      /* null/misaligned pointer, bad flag or value */
+    GG_ERR_UNSUPPORTED_SIZE = 2, /* N not supported by the kernels             */
+    GG_ERR_OUT_OF_MEMORY = 3,    /* plan tables could not be allocated         */
+    GG_ERR_HIP = 4,              /* a HIP runtime call or launch failed        */
+    GG_ERR_INTERNAL = 5
+} gg_status;
+
+typedef enum { GG_F32 = 0, GG_F64 = 1 } gg_dtype;
+
+/* Lattice: N cells per side (a power of two, 8 <= N <= 1024), box side L in
+ * Mpc/h. */
+typedef struct {
+    int32_t n;
+    double box;
+} gg_grid;
+
+/* Cosmology of the analytic spectrum P(k, z) = D(z)^2 A k^n_s T_BBKS(k)^2
+ * (BBKS fit, Gamma = omega_m h), sigma_8 at z = 0, Einstein-de Sitter growth
+ * D = 1/(1+z), flat-LCDM H(a), f = 1 (Sec. 2.1 footnote; Sec. 2.2).
+ * amp > 0 uses A = amp instead of the sigma_8 normalisation.
+ * lattice_offset is the Lagrangian point inside a cell, in cells (0.5 puts
+ * particles at cell centres as Sec. 2.2 describes). */
+typedef struct {
+    double omega_m;
+    double h;
+    double n_s;
+    double sigma8;
+    double z_init;
+    double amp;
+    double lattice_offset;
+} gg_cosmo;
+
+/* Read-only facts about a plan. */
+typedef struct {
+    int32_t n;
+    int32_t dtype;           /* gg_dtype */
+    double box;
+    double amplitude;        /* A at z = 0, from the FP64 sigma_8 integral */
+    double sigma8_integral;  /* sigma^2(8 Mpc/h) of the spectrum with A = 1 */
+    double growth;           /* D(z_init) */
+    double velocity_factor;  /* a H(a) f at z_init, km/s per Mpc/h */
+    size_t real_elems;       /* N^3 */
+    size_t spectrum_elems;   /* N N (N/2+1) complex values */
+    size_t workspace_bytes;  /* = gg_workspace_bytes(plan) */
+} gg_plan_info;
+
+typedef struct gg_plan gg_plan;
+
+/* Builds the device tables of a plan on the current HIP device: FP64-generated
+ * twiddles rounded to the dtype, the FP64 sigma_8 integral (Sec. 2.1
+ * footnote) evaluated on the GPU, and the table tau[n^2] of the filter of
+ * Eq. (1)-(2).  Synchronous.  *plan is set only on GG_OK.
+ * Errors: INVALID_ARG (null pointer, box <= 0, cosmology out of range),
+ * UNSUPPORTED_SIZE (N), OUT_OF_MEMORY, HIP. */
+gg_status gg_plan_create(gg_plan** plan, const gg_grid* grid, const gg_cosmo* cosmo, gg_dtype dtype);
+
+/* Frees the plan's tables (after synchronising its device).  NULL is a no-op. */
+gg_status gg_plan_destroy(gg_plan* plan);
+
+gg_status gg_plan_query(const gg_plan* plan, gg_plan_info* info);
+
+/* Bytes of device workspace that gg_make_ic and gg_fft3d need; 0 for a NULL
+ * plan. */
+size_t gg_workspace_bytes(const gg_plan* plan);
+
+/* White noise (Sec. 2, step 1): w[c] = N(0,1) deviate of cell c, c < N^3,
+ * in the plan's dtype.  w: R, written. */
+gg_status gg_noise(const gg_plan* plan, uint64_t seed, uint32_t stream_id, void* w, void* stream);
+
+/* 3D transform (Sec. 2.1).  dir = +1: in is R, out is H (unnormalised
+ * forward); work may be NULL.  dir = -1: in is H (a Hermitian half
+ * spectrum, left unmodified), out is R (normalised by 1/N^3); work must hold
+ * gg_workspace_bytes(plan).  in and out must not overlap. */
+gg_status gg_fft3d(const gg_plan* plan, int dir, const void* in, void* out, void* work, void* stream);
+
+/* Eq. (1) then Eq. (2): from the forward spectrum of the noise, writes the
+ * three displacement spectra psi~_j = i k_j/k^2 sqrt(P N^3/L^3) W~ into
+ * psi_spec (3 consecutive H arrays, component j at j N N (N/2+1)), and, if
+ * delta_spec is not NULL, delta~ = sqrt(P N^3/L^3) W~ (one H array). */
+gg_status gg_filter(const gg_plan* plan, const void* spec_in, void* psi_spec, void* delta_spec, void* stream);
+
+/* Eq. (3): from three displacement fields psi (3 consecutive R arrays),
+ * writes float32 positions x_j = wrap_L(q_j + psi_j) (sum in FP64, wrapped
+ * once into [0, L), a value rounding to L stored as 0) and velocities
+ * v_j = a H f psi_j, q_j = (m_j + lattice_offset) L/N.  Requires |psi| < L. */
+gg_status gg_zeldovich(const gg_plan* plan, const void* psi, float* pos, float* vel, void* stream);
+
+/* The whole path from a seed (stream_id 0): noise, forward transform, filter,
+ * three inverse transforms and Eq. (3), as five fused passes.  pos and vel as
+ * for gg_zeldovich; psi_opt, if not NULL, receives the three displacement
+ * fields (3 R arrays).  work must hold gg_workspace_bytes(plan). */
+gg_status gg_make_ic(const gg_plan* plan, uint64_t seed, float* pos, float* vel, void* psi_opt, void* work,
+                     void* stream);
+
+/* Per-pass timing of gg_make_ic with HIP events recorded on the call's
+ * stream.  Enable before the calls to time; gg_timing_read waits for the last
+ * recorded call and returns, for each of the npass passes, the summed
+ * milliseconds over the recorded calls, and the number of calls; it then
+ * clears the records.  While enabled the plan is not safe for concurrent
+ * calls.  npass is 5 (noise + forward z; forward y; forward x + filter +
+ * inverse x; inverse y; inverse z + particles). */
+gg_status gg_timing_enable(gg_plan* plan, int on);
+gg_status gg_timing_read(gg_plan* plan, double* ms_per_pass, int npass, int* ncalls);
+
+const char* gg_status_string(gg_status status);
+const char* gg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GG_H */

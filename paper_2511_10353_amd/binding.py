@@ -1,0 +1,217 @@
+"""ctypes binding of libgg (include/gg.h): argument marshalling only.
+
+Torch tensors supply device memory (``data_ptr``) and the current HIP stream;
+every step of the path runs in the library's kernels.  There is no fallback:
+if libgg.so is missing or no GPU is present, the calls raise.
+"""
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgg.so")
+
+GG_OK = 0
+STATUS_NAMES = {0: "GG_OK", 1: "GG_ERR_INVALID_ARG", 2: "GG_ERR_UNSUPPORTED_SIZE",
+                3: "GG_ERR_OUT_OF_MEMORY", 4: "GG_ERR_HIP", 5: "GG_ERR_INTERNAL"}
+DTYPES = {"f32": 0, "f64": 1}
+N_PASSES = 5
+
+
+class GGError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_double)]
+
+
+class _Cosmo(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("h", ctypes.c_double), ("n_s", ctypes.c_double),
+                ("sigma8", ctypes.c_double), ("z_init", ctypes.c_double), ("amp", ctypes.c_double),
+                ("lattice_offset", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("box", ctypes.c_double),
+                ("amplitude", ctypes.c_double), ("sigma8_integral", ctypes.c_double),
+                ("growth", ctypes.c_double), ("velocity_factor", ctypes.c_double),
+                ("real_elems", ctypes.c_size_t), ("spectrum_elems", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+@dataclasses.dataclass
+class Cosmo:
+    """Spectrum parameters (defaults: Omega_m 0.3, h 0.7, n_s 0.96, sigma_8 0.8, z 100)."""
+    omega_m: float = 0.3
+    h: float = 0.7
+    n_s: float = 0.96
+    sigma8: float = 0.8
+    z_init: float = 100.0
+    amp: float = 0.0
+    lattice_offset: float = 0.5
+
+    def _c(self):
+        return _Cosmo(self.omega_m, self.h, self.n_s, self.sigma8, self.z_init, self.amp, self.lattice_offset)
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "gg_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(_Grid), ctypes.POINTER(_Cosmo), ctypes.c_int]),
+    "gg_plan_destroy": (ctypes.c_int, [_VP]),
+    "gg_plan_query": (ctypes.c_int, [_VP, ctypes.POINTER(_Info)]),
+    "gg_workspace_bytes": (ctypes.c_size_t, [_VP]),
+    "gg_noise": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP]),
+    "gg_fft3d": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP, _VP]),
+    "gg_filter": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "gg_zeldovich": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "gg_make_ic": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP]),
+    "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "gg_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]),
+    "gg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gg_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libgg.so (built by paper_2511_10353_amd.build) once."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2511_10353_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status):
+    if status != GG_OK:
+        raise GGError(status, lib().gg_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """One lattice (N, L), cosmology and precision; owns the device tables."""
+
+    def __init__(self, n, box, cosmo=None, dtype="f32"):
+        if dtype not in DTYPES:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgg needs a ROCm GPU; torch.cuda.is_available() is False")
+        torch.cuda.init()
+        self.n = int(n)
+        self.box = float(box)
+        self.cosmo = cosmo or Cosmo()
+        self.dtype = dtype
+        self.real_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.complex_dtype = torch.complex64 if dtype == "f32" else torch.complex128
+        self._h = ctypes.c_void_p()
+        _check(lib().gg_plan_create(ctypes.byref(self._h), ctypes.byref(_Grid(self.n, self.box)),
+                                    ctypes.byref(self.cosmo._c()), DTYPES[dtype]))
+        info = _Info()
+        _check(lib().gg_plan_query(self._h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.workspace_bytes = int(lib().gg_workspace_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            lib().gg_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ---------------------------------------------------------------
+    def _real_shape(self):
+        return (self.n, self.n, self.n)
+
+    def _spec_shape(self):
+        return (self.n, self.n, self.n // 2 + 1)
+
+    def _need(self, t, shape, dtype, name):
+        if t is None:
+            return torch.empty(shape, dtype=dtype, device="cuda")
+        if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous cuda tensor {tuple(shape)} {dtype}, "
+                             f"got {tuple(t.shape)} {t.dtype} cuda={t.is_cuda}")
+        return t
+
+    def workspace(self):
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+
+    # -- entry points ------------------------------------------------------------
+    def noise(self, seed, out=None, stream_id=0):
+        out = self._need(out, self._real_shape(), self.real_dtype, "out")
+        _check(lib().gg_noise(self._h, int(seed), int(stream_id), _ptr(out), _stream()))
+        return out
+
+    def fft3d(self, x, direction, out=None, work=None):
+        if direction == 1:
+            x = self._need(x, self._real_shape(), self.real_dtype, "x")
+            out = self._need(out, self._spec_shape(), self.complex_dtype, "out")
+        elif direction == -1:
+            x = self._need(x, self._spec_shape(), self.complex_dtype, "x")
+            out = self._need(out, self._real_shape(), self.real_dtype, "out")
+            if work is None:
+                work = self.workspace()
+        else:
+            raise ValueError("direction must be +1 or -1")
+        _check(lib().gg_fft3d(self._h, int(direction), _ptr(x), _ptr(out), _ptr(work), _stream()))
+        return out
+
+    def filter(self, spec, psi=None, delta=None, want_delta=False):
+        spec = self._need(spec, self._spec_shape(), self.complex_dtype, "spec")
+        psi = self._need(psi, (3,) + self._spec_shape(), self.complex_dtype, "psi")
+        if want_delta or delta is not None:
+            delta = self._need(delta, self._spec_shape(), self.complex_dtype, "delta")
+        _check(lib().gg_filter(self._h, _ptr(spec), _ptr(psi), _ptr(delta), _stream()))
+        return (psi, delta) if delta is not None else psi
+
+    def zeldovich(self, psi, pos=None, vel=None):
+        psi = self._need(psi, (3,) + self._real_shape(), self.real_dtype, "psi")
+        pos = self._need(pos, (3,) + self._real_shape(), torch.float32, "pos")
+        vel = self._need(vel, (3,) + self._real_shape(), torch.float32, "vel")
+        _check(lib().gg_zeldovich(self._h, _ptr(psi), _ptr(pos), _ptr(vel), _stream()))
+        return pos, vel
+
+    def make_ic(self, seed, pos=None, vel=None, psi=None, work=None, want_psi=False):
+        pos = self._need(pos, (3,) + self._real_shape(), torch.float32, "pos")
+        vel = self._need(vel, (3,) + self._real_shape(), torch.float32, "vel")
+        if want_psi or psi is not None:
+            psi = self._need(psi, (3,) + self._real_shape(), self.real_dtype, "psi")
+        if work is None:
+            work = self.workspace()
+        elif work.numel() * work.element_size() < self.workspace_bytes or not work.is_cuda:
+            raise ValueError("work buffer too small")
+        _check(lib().gg_make_ic(self._h, int(seed), _ptr(pos), _ptr(vel), _ptr(psi), _ptr(work), _stream()))
+        return (pos, vel, psi) if psi is not None else (pos, vel)
+
+    def timing_enable(self, on=True):
+        _check(lib().gg_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        ms = (ctypes.c_double * N_PASSES)()
+        calls = ctypes.c_int(0)
+        _check(lib().gg_timing_read(self._h, ms, N_PASSES, ctypes.byref(calls)))
+        return [ms[i] for i in range(N_PASSES)], calls.value

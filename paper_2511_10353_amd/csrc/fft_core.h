@@ -1,0 +1,237 @@
+// Batched in-LDS Stockham FFT building blocks for gfx950 (wave64).
+//
+// A work-group transforms L independent lines of M complex points.  Lines
+// are the columns of an LDS tile of M rows x L columns; element (row, col)
+// lives at row * L + (col ^ (row & (L - 1))).  L complex values of one row
+// span 128 bytes (L = 16 for float, 8 for double), so every access in which
+// each aligned group of L lanes touches one row (the c-fastest thread
+// mapping used by all butterfly stages) or one column over L consecutive
+// rows (the contiguous copies of the z passes) hits every LDS bank once.
+//
+// Thread t of the group works on line c = t % L as the j = t / L-th of
+// TPL = M / RMAX threads of that line; it holds RMAX complex values in
+// registers.  A stage of radix R with sub-length NS (product of the radices
+// already applied) performs, for butterfly b in [0, M/R), k = b mod NS:
+//   a_r = x[b + r M/R] * W_{NS R}^{r k},  A = DFT_R(a),
+//   y[(b - k) R + k + r NS] = A_r,
+// which leaves the result in natural order after the last stage (Stockham
+// autosort).  The first stage takes its inputs from registers and the last
+// stage leaves its outputs in registers, so a strided pass moves data between
+// HBM and registers directly and uses LDS only for the exchanges in between.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gg {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> w) { return {a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x}; }
+// a * conj(w)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> w) { return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y}; }
+// a * i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
+// a * (DIR i): DIR = -1 is a quarter turn of the forward transform
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+    if constexpr (DIR < 0) return {a.y, -a.x};
+    else return {-a.y, a.x};
+}
+// a * W where W = (wr, DIR * wi) with compile-time constants
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> cmul_dir(cx<T> a, T wr, T wi) {
+    const T s = (DIR < 0) ? -wi : wi;
+    return {a.x * wr - a.y * s, a.x * s + a.y * wr};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers: X_k = sum_n a_n exp(DIR 2 pi i n k / R).
+// ---------------------------------------------------------------------------
+constexpr double kSqrtHalf = 0.70710678118654752440;
+constexpr double kCos8 = 0.92387953251128675613;  // cos(pi/8)
+constexpr double kSin8 = 0.38268343236508977173;  // sin(pi/8)
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>& a0, cx<T>& a1) {
+    cx<T> t = a0;
+    a0 = cadd(t, a1);
+    a1 = csub(t, a1);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+    cx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    cx<T> t2 = cadd(a1, a3), t3 = rot90<DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cx<T>* a) {
+    const T h = (T)kSqrtHalf;
+    dft4<DIR>(a[0], a[2], a[4], a[6]);
+    dft4<DIR>(a[1], a[3], a[5], a[7]);
+    cx<T> o1 = cmul_dir<DIR>(a[3], h, h);
+    cx<T> o2 = rot90<DIR>(a[5]);
+    cx<T> o3 = cmul_dir<DIR>(a[7], -h, h);
+    cx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
+    a[0] = cadd(e0, o0);
+    a[4] = csub(e0, o0);
+    a[1] = cadd(e1, o1);
+    a[5] = csub(e1, o1);
+    a[2] = cadd(e2, o2);
+    a[6] = csub(e2, o2);
+    a[3] = cadd(e3, o3);
+    a[7] = csub(e3, o3);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft16(cx<T>* a) {
+    // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle W16^(n2 k1), DFT4 over n2
+    const T h = (T)kSqrtHalf, c8 = (T)kCos8, s8 = (T)kSin8;
+    dft4<DIR>(a[0], a[4], a[8], a[12]);
+    dft4<DIR>(a[1], a[5], a[9], a[13]);
+    dft4<DIR>(a[2], a[6], a[10], a[14]);
+    dft4<DIR>(a[3], a[7], a[11], a[15]);
+    // a[4 k1 + n2] now holds Y[n2][k1]
+    a[5] = cmul_dir<DIR>(a[5], c8, s8);     // n2=1,k1=1: W^1
+    a[6] = cmul_dir<DIR>(a[6], h, h);       // n2=2,k1=1: W^2
+    a[7] = cmul_dir<DIR>(a[7], s8, c8);     // n2=3,k1=1: W^3
+    a[9] = cmul_dir<DIR>(a[9], h, h);       // n2=1,k1=2: W^2
+    a[10] = rot90<DIR>(a[10]);              // n2=2,k1=2: W^4
+    a[11] = cmul_dir<DIR>(a[11], -h, h);    // n2=3,k1=2: W^6
+    a[13] = cmul_dir<DIR>(a[13], s8, c8);   // n2=1,k1=3: W^3
+    a[14] = cmul_dir<DIR>(a[14], -h, h);    // n2=2,k1=3: W^6
+    a[15] = cmul_dir<DIR>(a[15], -c8, -s8); // n2=3,k1=3: W^9
+    dft4<DIR>(a[0], a[1], a[2], a[3]);
+    dft4<DIR>(a[4], a[5], a[6], a[7]);
+    dft4<DIR>(a[8], a[9], a[10], a[11]);
+    dft4<DIR>(a[12], a[13], a[14], a[15]);
+    // a[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4x4 index
+    cx<T> t;
+#define GG_SWAP(p, q) t = a[p]; a[p] = a[q]; a[q] = t;
+    GG_SWAP(1, 4) GG_SWAP(2, 8) GG_SWAP(3, 12) GG_SWAP(6, 9) GG_SWAP(7, 13) GG_SWAP(11, 14)
+#undef GG_SWAP
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T>* a) {
+    if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
+    else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+    else if constexpr (R == 8) dft8<DIR>(a);
+    else if constexpr (R == 16) dft16<DIR>(a);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// Radix plans: line length M -> radices of the forward transform (the inverse
+// applies them in reverse order so that its first stage reads the positions
+// the forward's last stage leaves in registers).
+// ---------------------------------------------------------------------------
+template <int M> struct Plan;
+template <> struct Plan<4>    { static constexpr int S = 1; static constexpr int R[1] = {4}; };
+template <> struct Plan<8>    { static constexpr int S = 1; static constexpr int R[1] = {8}; };
+template <> struct Plan<16>   { static constexpr int S = 1; static constexpr int R[1] = {16}; };
+template <> struct Plan<32>   { static constexpr int S = 2; static constexpr int R[2] = {8, 4}; };
+template <> struct Plan<64>   { static constexpr int S = 2; static constexpr int R[2] = {8, 8}; };
+template <> struct Plan<128>  { static constexpr int S = 2; static constexpr int R[2] = {16, 8}; };
+template <> struct Plan<256>  { static constexpr int S = 2; static constexpr int R[2] = {16, 16}; };
+template <> struct Plan<512>  { static constexpr int S = 3; static constexpr int R[3] = {8, 8, 8}; };
+template <> struct Plan<1024> { static constexpr int S = 3; static constexpr int R[3] = {16, 4, 16}; };
+
+template <int M>
+struct PlanInfo {
+    static constexpr int rmax() {
+        int r = 0;
+        for (int s = 0; s < Plan<M>::S; ++s) r = Plan<M>::R[s] > r ? Plan<M>::R[s] : r;
+        return r;
+    }
+    static constexpr int RMAX = rmax();
+    static constexpr int TPL = M / RMAX;  // threads per line
+    static constexpr int V = RMAX;        // complex values held per thread
+    template <int DIR>
+    static constexpr int first_radix() { return DIR < 0 ? Plan<M>::R[0] : Plan<M>::R[Plan<M>::S - 1]; }
+    template <int DIR>
+    static constexpr int last_radix() { return DIR < 0 ? Plan<M>::R[Plan<M>::S - 1] : Plan<M>::R[0]; }
+};
+
+// Position (row) of register slot i of thread j before the first stage ...
+template <int M, int DIR>
+__device__ __forceinline__ int first_pos(int j, int i) {
+    constexpr int R = PlanInfo<M>::template first_radix<DIR>();
+    return j + PlanInfo<M>::TPL * (i / R) + (i % R) * (M / R);
+}
+// ... and after the last stage.
+template <int M, int DIR>
+__device__ __forceinline__ int last_pos(int j, int i) {
+    constexpr int R = PlanInfo<M>::template last_radix<DIR>();
+    return j + PlanInfo<M>::TPL * (i / R) + (i % R) * (M / R);
+}
+
+template <int L>
+__device__ __forceinline__ int lidx(int row, int col) { return row * L + (col ^ (row & (L - 1))); }
+
+// One Stockham stage (see the file header).  tw[m * TWS] = exp(-2 pi i m / M).
+template <typename T, int M, int L, int R, int NS, int DIR, int TWS, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_stage(cx<T>* v, cx<T>* lds, const cx<T>* __restrict__ tw, int c, int j) {
+    constexpr int TPL = PlanInfo<M>::TPL;
+    constexpr int BPT = PlanInfo<M>::RMAX / R;
+    constexpr int NB = M / R;
+    if constexpr (!FIRST) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u * R + r] = lds[lidx<L>(j + TPL * u + r * NB, c)];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int b = j + TPL * u;
+        const int k = b & (NS - 1);
+        if constexpr (!FIRST) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cx<T> w = tw[(r * k * (M / (NS * R))) * TWS];
+                v[u * R + r] = (DIR < 0) ? cmul(v[u * R + r], w) : cmulc(v[u * R + r], w);
+            }
+        }
+        dft<R, DIR>(v + u * R);
+        if constexpr (!LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lidx<L>((b - k) * R + k + r * NS, c)] = v[u * R + r];
+        }
+    }
+    if constexpr (!LAST) __syncthreads();
+}
+
+// Full transform of one line per column: inputs in v at first_pos, outputs
+// in v at last_pos.  On return every thread has finished with LDS.
+template <typename T, int M, int L, int DIR, int TWS, int s = 0, int NS = 1>
+__device__ __forceinline__ void fft_lines(cx<T>* v, cx<T>* lds, const cx<T>* __restrict__ tw, int c, int j) {
+    constexpr int S = Plan<M>::S;
+    constexpr int R = (DIR < 0) ? Plan<M>::R[s] : Plan<M>::R[S - 1 - s];
+    stockham_stage<T, M, L, R, NS, DIR, TWS, (s == 0), (s == S - 1)>(v, lds, tw, c, j);
+    if constexpr (s + 1 < S) fft_lines<T, M, L, DIR, TWS, s + 1, NS * R>(v, lds, tw, c, j);
+}
+
+// Lines per work-group: one 128-byte LDS row of complex values.
+template <typename T>
+struct Tile {
+    static constexpr int L = 128 / (2 * sizeof(T));
+};
+
+}  // namespace gg

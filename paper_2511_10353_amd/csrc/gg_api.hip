@@ -1,0 +1,423 @@
+// C ABI of the initial-conditions library (declared in include/gg.h):
+// argument validation, plan construction (FP64 twiddles, the GPU sigma_8
+// integral and the tau table) and dispatch to the per-type launchers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gg.h"
+#include "kernels.h"
+#include "ops.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gg_status fail(gg_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+gg_status fail_hip(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return GG_ERR_HIP;
+}
+
+constexpr int kTimingSlots = 256;  // calls recorded per gg_timing_read
+constexpr int kPasses = 5;
+
+}  // namespace
+
+struct gg_plan {
+    int n = 0;
+    double box = 0;
+    gg_dtype dtype = GG_F32;
+    gg_cosmo cosmo{};
+    int device = 0;
+    void* tw = nullptr;    // N complex values of the dtype
+    void* tau = nullptr;   // ntau values of the dtype
+    int64_t ntau = 0;
+    double amplitude = 0, sigma_int = 0, growth = 0, vfac = 0, cell = 0;
+    // timing records
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // kTimingSlots * (kPasses + 1)
+    int recorded = 0;
+};
+
+namespace {
+
+bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+template <typename T>
+gg::PlanView<T> view(const gg_plan* p) {
+    gg::PlanView<T> v;
+    v.n = p->n;
+    v.box = p->box;
+    v.cell = p->cell;
+    v.offset = p->cosmo.lattice_offset;
+    v.vfac = p->vfac;
+    v.tw = static_cast<const gg::cx<T>*>(p->tw);
+    v.tau = static_cast<const T*>(p->tau);
+    return v;
+}
+
+size_t elem_size(gg_dtype d) { return d == GG_F64 ? sizeof(double) : sizeof(float); }
+
+gg_status check_device(const gg_plan* p) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != p->device) return fail(GG_ERR_INVALID_ARG, "current HIP device differs from the plan's device");
+    return GG_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Twiddles exp(-2 pi i m / N) in extended precision, rounded to the dtype.
+template <typename T>
+std::vector<gg::cx<T>> make_twiddles(int n) {
+    std::vector<gg::cx<T>> tw(n);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int m = 0; m < n; ++m) {
+        // reduce to the first octant so that special angles come out exact
+        int k = m % n;
+        long double c, s;
+        const int q = (4 * k) / n;           // quadrant
+        const int r = 4 * k - q * n;         // 4 * angle within quadrant, in units of 2 pi / (4 n)
+        const long double a = two_pi * (long double)r / (4.0L * n);
+        const long double ca = cosl(a), sa = sinl(a);
+        switch (q) {
+            case 0: c = ca; s = sa; break;
+            case 1: c = -sa; s = ca; break;
+            case 2: c = -ca; s = -sa; break;
+            default: c = sa; s = -ca; break;
+        }
+        tw[m] = {(T)(double)c, (T)(double)(-s)};
+    }
+    return tw;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gg_status_string(gg_status st) {
+    switch (st) {
+        case GG_OK: return "GG_OK";
+        case GG_ERR_INVALID_ARG: return "GG_ERR_INVALID_ARG";
+        case GG_ERR_UNSUPPORTED_SIZE: return "GG_ERR_UNSUPPORTED_SIZE";
+        case GG_ERR_OUT_OF_MEMORY: return "GG_ERR_OUT_OF_MEMORY";
+        case GG_ERR_HIP: return "GG_ERR_HIP";
+        case GG_ERR_INTERNAL: return "GG_ERR_INTERNAL";
+    }
+    return "GG_ERR_UNKNOWN";
+}
+
+const char* gg_last_error(void) { return g_last_error.c_str(); }
+
+size_t gg_workspace_bytes(const gg_plan* p) {
+    if (!p) return 0;
+    size_t a, b;
+    if (p->dtype == GG_F64) {
+        a = gg::Ops<double>::fused_work_bytes(p->n);
+        b = gg::Ops<double>::inverse_work_bytes(p->n);
+    } else {
+        a = gg::Ops<float>::fused_work_bytes(p->n);
+        b = gg::Ops<float>::inverse_work_bytes(p->n);
+    }
+    return a > b ? a : b;
+}
+
+gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cosmo, gg_dtype dtype) {
+    g_last_error.clear();
+    if (!out || !grid || !cosmo) return fail(GG_ERR_INVALID_ARG, "null argument to gg_plan_create");
+    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "dtype must be GG_F32 or GG_F64");
+    if (!gg::supported_n(grid->n))
+        return fail(GG_ERR_UNSUPPORTED_SIZE, "N must be a power of two in [8, 1024], got " + std::to_string(grid->n));
+    const gg_cosmo& c = *cosmo;
+    if (!(grid->box > 0) || !std::isfinite(grid->box)) return fail(GG_ERR_INVALID_ARG, "box must be > 0");
+    if (!(c.omega_m > 0 && c.omega_m <= 1)) return fail(GG_ERR_INVALID_ARG, "omega_m must be in (0, 1]");
+    if (!(c.h > 0) || !std::isfinite(c.h)) return fail(GG_ERR_INVALID_ARG, "h must be > 0");
+    if (!std::isfinite(c.n_s)) return fail(GG_ERR_INVALID_ARG, "n_s must be finite");
+    if (!(c.z_init > -1) || !std::isfinite(c.z_init)) return fail(GG_ERR_INVALID_ARG, "z_init must be > -1");
+    if (!(c.amp >= 0) || !std::isfinite(c.amp)) return fail(GG_ERR_INVALID_ARG, "amp must be >= 0");
+    if (c.amp == 0 && !(c.sigma8 > 0)) return fail(GG_ERR_INVALID_ARG, "sigma8 must be > 0 when amp = 0");
+    if (!std::isfinite(c.lattice_offset)) return fail(GG_ERR_INVALID_ARG, "lattice_offset must be finite");
+
+    gg_plan* p = new (std::nothrow) gg_plan();
+    if (!p) return fail(GG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->n = grid->n;
+    p->box = grid->box;
+    p->dtype = dtype;
+    p->cosmo = c;
+    p->cell = grid->box / (double)grid->n;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "hipGetDevice");
+    }
+    const size_t es = elem_size(dtype);
+    const int half = p->n / 2;
+    p->ntau = 3LL * half * half + 1;
+    double* d_sig = nullptr;
+    hipStream_t s = nullptr;
+    gg_status st = GG_OK;
+    auto cleanup = [&]() {
+        if (d_sig) hipFree(d_sig);
+        if (s) hipStreamDestroy(s);
+    };
+    do {
+        if ((e = hipMalloc(&p->tw, 2 * es * p->n)) != hipSuccess ||
+            (e = hipMalloc(&p->tau, es * p->ntau)) != hipSuccess || (e = hipMalloc(&d_sig, sizeof(double))) != hipSuccess) {
+            st = fail(GG_ERR_OUT_OF_MEMORY, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
+            break;
+        }
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
+            st = fail_hip(e, "hipStreamCreate");
+            break;
+        }
+        if (dtype == GG_F64) {
+            auto tw = make_twiddles<double>(p->n);
+            e = hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        } else {
+            auto tw = make_twiddles<float>(p->n);
+            e = hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (e != hipSuccess) {
+            st = fail_hip(e, "twiddle upload");
+            break;
+        }
+        const double gamma = c.omega_m * c.h;
+        e = gg::launch_sigma_integral(std::log(1e-5), std::log(1e3), gamma, c.n_s, 8.0, d_sig, s);
+        double sig = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&sig, d_sig, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = fail_hip(e, "sigma_8 integral");
+            break;
+        }
+        if (!(sig > 0) || !std::isfinite(sig)) {
+            st = fail(GG_ERR_INTERNAL, "sigma_8 integral is not positive");
+            break;
+        }
+        p->sigma_int = sig;
+        p->amplitude = c.amp > 0 ? c.amp : c.sigma8 * c.sigma8 / sig;
+        p->growth = 1.0 / (1.0 + c.z_init);
+        const double a = 1.0 / (1.0 + c.z_init);
+        p->vfac = a * (100.0 * std::sqrt(c.omega_m / std::pow(a, 3.0) + 1.0 - c.omega_m)) * 1.0;
+        const double ag2 = p->amplitude * p->growth * p->growth;
+        if (dtype == GG_F64)
+            e = gg::Ops<double>::tau_table(static_cast<double*>(p->tau), p->ntau, p->n, p->box, ag2, gamma, c.n_s, s);
+        else
+            e = gg::Ops<float>::tau_table(static_cast<float*>(p->tau), p->ntau, p->n, p->box, ag2, gamma, c.n_s, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = fail_hip(e, "tau table");
+            break;
+        }
+    } while (false);
+    cleanup();
+    if (st != GG_OK) {
+        if (p->tw) hipFree(p->tw);
+        if (p->tau) hipFree(p->tau);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return GG_OK;
+}
+
+gg_status gg_plan_destroy(gg_plan* p) {
+    if (!p) return GG_OK;
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (cur != p->device) hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    for (hipEvent_t ev : p->events) hipEventDestroy(ev);
+    if (p->tw) hipFree(p->tw);
+    if (p->tau) hipFree(p->tau);
+    if (cur >= 0 && cur != p->device) hipSetDevice(cur);
+    delete p;
+    return GG_OK;
+}
+
+gg_status gg_plan_query(const gg_plan* p, gg_plan_info* info) {
+    if (!p || !info) return fail(GG_ERR_INVALID_ARG, "null argument to gg_plan_query");
+    info->n = p->n;
+    info->dtype = p->dtype;
+    info->box = p->box;
+    info->amplitude = p->amplitude;
+    info->sigma8_integral = p->sigma_int;
+    info->growth = p->growth;
+    info->velocity_factor = p->vfac;
+    info->real_elems = (size_t)p->n * p->n * p->n;
+    info->spectrum_elems = (size_t)p->n * p->n * (p->n / 2 + 1);
+    info->workspace_bytes = gg_workspace_bytes(p);
+    return GG_OK;
+}
+
+gg_status gg_noise(const gg_plan* p, uint64_t seed, uint32_t stream_id, void* w, void* stream) {
+    if (!p || !w) return fail(GG_ERR_INVALID_ARG, "null argument to gg_noise");
+    if (!aligned(w)) return fail(GG_ERR_INVALID_ARG, "w must be 256-byte aligned");
+    gg_status st = check_device(p);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = p->dtype == GG_F64
+                       ? gg::Ops<double>::noise(view<double>(p), seed, stream_id, static_cast<double*>(w), s)
+                       : gg::Ops<float>::noise(view<float>(p), seed, stream_id, static_cast<float*>(w), s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "noise launch");
+}
+
+gg_status gg_fft3d(const gg_plan* p, int dir, const void* in, void* out, void* work, void* stream) {
+    if (!p || !in || !out) return fail(GG_ERR_INVALID_ARG, "null argument to gg_fft3d");
+    if (dir != 1 && dir != -1) return fail(GG_ERR_INVALID_ARG, "dir must be +1 or -1");
+    if (!aligned(in) || !aligned(out)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t es = elem_size(p->dtype);
+    const size_t rbytes = es * p->n * p->n * p->n;
+    const size_t hbytes = 2 * es * p->n * p->n * (p->n / 2 + 1);
+    if (dir == 1 ? overlap(in, rbytes, out, hbytes) : overlap(in, hbytes, out, rbytes))
+        return fail(GG_ERR_INVALID_ARG, "in and out must not overlap");
+    if (dir == -1) {
+        if (!work) return fail(GG_ERR_INVALID_ARG, "the inverse transform needs a work buffer");
+        if (!aligned(work)) return fail(GG_ERR_INVALID_ARG, "work must be 256-byte aligned");
+        if (overlap(work, hbytes, in, hbytes) || overlap(work, hbytes, out, rbytes))
+            return fail(GG_ERR_INVALID_ARG, "work must not overlap in or out");
+    }
+    gg_status st = check_device(p);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (p->dtype == GG_F64) {
+        using C = gg::cx<double>;
+        e = dir == 1 ? gg::Ops<double>::fft_forward(view<double>(p), static_cast<const double*>(in), static_cast<C*>(out), s)
+                     : gg::Ops<double>::fft_inverse(view<double>(p), static_cast<const C*>(in), static_cast<double*>(out),
+                                                     static_cast<C*>(work), s);
+    } else {
+        using C = gg::cx<float>;
+        e = dir == 1 ? gg::Ops<float>::fft_forward(view<float>(p), static_cast<const float*>(in), static_cast<C*>(out), s)
+                     : gg::Ops<float>::fft_inverse(view<float>(p), static_cast<const C*>(in), static_cast<float*>(out),
+                                                    static_cast<C*>(work), s);
+    }
+    return e == hipSuccess ? GG_OK : fail_hip(e, "fft3d launch");
+}
+
+gg_status gg_filter(const gg_plan* p, const void* spec_in, void* psi_spec, void* delta_spec, void* stream) {
+    if (!p || !spec_in || !psi_spec) return fail(GG_ERR_INVALID_ARG, "null argument to gg_filter");
+    if (!aligned(spec_in) || !aligned(psi_spec) || (delta_spec && !aligned(delta_spec)))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t hbytes = 2 * elem_size(p->dtype) * p->n * p->n * (p->n / 2 + 1);
+    if (overlap(spec_in, hbytes, psi_spec, 3 * hbytes) || (delta_spec && overlap(spec_in, hbytes, delta_spec, hbytes)) ||
+        (delta_spec && overlap(psi_spec, 3 * hbytes, delta_spec, hbytes)))
+        return fail(GG_ERR_INVALID_ARG, "filter buffers must not overlap");
+    gg_status st = check_device(p);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (p->dtype == GG_F64) {
+        using C = gg::cx<double>;
+        e = gg::Ops<double>::filter(view<double>(p), static_cast<const C*>(spec_in), static_cast<C*>(psi_spec),
+                                    static_cast<C*>(delta_spec), s);
+    } else {
+        using C = gg::cx<float>;
+        e = gg::Ops<float>::filter(view<float>(p), static_cast<const C*>(spec_in), static_cast<C*>(psi_spec),
+                                   static_cast<C*>(delta_spec), s);
+    }
+    return e == hipSuccess ? GG_OK : fail_hip(e, "filter launch");
+}
+
+gg_status gg_zeldovich(const gg_plan* p, const void* psi, float* pos, float* vel, void* stream) {
+    if (!p || !psi || !pos || !vel) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zeldovich");
+    if (!aligned(psi) || !aligned(pos) || !aligned(vel))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t n3 = (size_t)p->n * p->n * p->n;
+    if (overlap(pos, 12 * n3, vel, 12 * n3) || overlap(psi, 3 * n3 * elem_size(p->dtype), pos, 12 * n3) ||
+        overlap(psi, 3 * n3 * elem_size(p->dtype), vel, 12 * n3))
+        return fail(GG_ERR_INVALID_ARG, "psi, pos and vel must not overlap");
+    gg_status st = check_device(p);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = p->dtype == GG_F64
+                       ? gg::Ops<double>::zeldovich(view<double>(p), static_cast<const double*>(psi), pos, vel, s)
+                       : gg::Ops<float>::zeldovich(view<float>(p), static_cast<const float*>(psi), pos, vel, s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "zeldovich launch");
+}
+
+gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, void* psi_opt, void* work,
+                     void* stream) {
+    if (!pc || !pos || !vel || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_make_ic");
+    if (!aligned(pos) || !aligned(vel) || !aligned(work) || (psi_opt && !aligned(psi_opt)))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t n3 = (size_t)pc->n * pc->n * pc->n;
+    const size_t wb = gg_workspace_bytes(pc);
+    const size_t pb = psi_opt ? 3 * n3 * elem_size(pc->dtype) : 0;
+    if (overlap(pos, 12 * n3, vel, 12 * n3) || overlap(work, wb, pos, 12 * n3) || overlap(work, wb, vel, 12 * n3) ||
+        (psi_opt && (overlap(psi_opt, pb, work, wb) || overlap(psi_opt, pb, pos, 12 * n3) ||
+                     overlap(psi_opt, pb, vel, 12 * n3))))
+        return fail(GG_ERR_INVALID_ARG, "pos, vel, psi and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    gg_plan* p = const_cast<gg_plan*>(pc);  // timing records are the plan's only mutable state
+    hipEvent_t* ev = nullptr;
+    if (p->timing && p->recorded < kTimingSlots) {
+        ev = &p->events[(size_t)p->recorded * (kPasses + 1)];
+        p->recorded++;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (p->dtype == GG_F64)
+        e = gg::Ops<double>::make_ic(view<double>(p), seed, pos, vel, static_cast<double*>(psi_opt),
+                                     static_cast<gg::cx<double>*>(work), s, ev);
+    else
+        e = gg::Ops<float>::make_ic(view<float>(p), seed, pos, vel, static_cast<float*>(psi_opt),
+                                    static_cast<gg::cx<float>*>(work), s, ev);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic launch");
+}
+
+gg_status gg_timing_enable(gg_plan* p, int on) {
+    if (!p) return fail(GG_ERR_INVALID_ARG, "null plan");
+    if (on && p->events.empty()) {
+        p->events.resize((size_t)kTimingSlots * (kPasses + 1));
+        for (auto& ev : p->events) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return fail_hip(e, "hipEventCreate");
+        }
+    }
+    p->timing = on != 0;
+    p->recorded = 0;
+    return GG_OK;
+}
+
+gg_status gg_timing_read(gg_plan* p, double* ms, int npass, int* ncalls) {
+    if (!p || !ms || !ncalls) return fail(GG_ERR_INVALID_ARG, "null argument to gg_timing_read");
+    if (npass != kPasses) return fail(GG_ERR_INVALID_ARG, "npass must be 5");
+    for (int i = 0; i < npass; ++i) ms[i] = 0;
+    *ncalls = p->recorded;
+    if (p->recorded == 0) return GG_OK;
+    hipError_t e = hipEventSynchronize(p->events[(size_t)(p->recorded - 1) * (kPasses + 1) + kPasses]);
+    if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    for (int r = 0; r < p->recorded; ++r) {
+        for (int i = 0; i < kPasses; ++i) {
+            float t = 0;
+            e = hipEventElapsedTime(&t, p->events[(size_t)r * (kPasses + 1) + i],
+                                    p->events[(size_t)r * (kPasses + 1) + i + 1]);
+            if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+            ms[i] += t;
+        }
+    }
+    p->recorded = 0;
+    return GG_OK;
+}
+
+}  // extern "C"

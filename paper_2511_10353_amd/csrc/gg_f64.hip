@@ -1,0 +1,38 @@
+// Double-precision instantiation of the kernels and launchers, and the FP64
+// sigma_8 integral.
+#include "ops_impl.h"
+
+namespace gg {
+template struct Ops<double>;
+
+// out[0] = S (the sigma^2(8 Mpc/h) of the spectrum with A = 1)
+__global__ __launch_bounds__(kSigmaThreads) void k_sigma_integral(double lnk_min, double lnk_max, double gamma,
+                                                                   double n_s, double radius, double* out) {
+    __shared__ double part[kSigmaThreads];
+    const double h = (lnk_max - lnk_min) / kSimpsonIntervals;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i <= kSimpsonIntervals; i += kSigmaThreads) {
+        const double lnk = (i == kSimpsonIntervals) ? lnk_max : lnk_min + (double)i * h;
+        const double k = exp(lnk);
+        const double t = bbks(k, gamma);
+        const double w = tophat(k * radius);
+        const double f = k * k * k * pow(k, n_s) * t * t * w * w;
+        const double wt = (i == 0 || i == kSimpsonIntervals) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+        acc += wt * f;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kSigmaThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0] * h / 3.0 / (2.0 * kPi * kPi);
+}
+
+
+hipError_t launch_sigma_integral(double lnk_min, double lnk_max, double gamma, double n_s, double radius,
+                                 double* out, hipStream_t s) {
+    k_sigma_integral<<<1, kSigmaThreads, 0, s>>>(lnk_min, lnk_max, gamma, n_s, radius, out);
+    return hipGetLastError();
+}
+}  // namespace gg

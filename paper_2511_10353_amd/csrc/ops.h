@@ -1,0 +1,42 @@
+// Host-side launchers of the kernels, per arithmetic type.  Declared here,
+// defined (and explicitly instantiated) in gg_f32.hip and gg_f64.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.h"
+
+namespace gg {
+
+template <typename T>
+struct PlanView;
+
+// Lattice sizes the kernels are instantiated for.
+constexpr bool supported_n(int n) {
+    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
+}
+
+template <typename T>
+struct Ops {
+    static hipError_t noise(const PlanView<T>& pv, uint64_t seed, uint32_t stream_id, T* w, hipStream_t s);
+    static hipError_t fft_forward(const PlanView<T>& pv, const T* in, cx<T>* out, hipStream_t s);
+    static hipError_t fft_inverse(const PlanView<T>& pv, const cx<T>* in, T* out, cx<T>* work, hipStream_t s);
+    static hipError_t filter(const PlanView<T>& pv, const cx<T>* w, cx<T>* psi, cx<T>* delta, hipStream_t s);
+    static hipError_t zeldovich(const PlanView<T>& pv, const T* psi, float* pos, float* vel, hipStream_t s);
+    // ev: null, or 6 events recorded before P1 and after each of P1..P5
+    static hipError_t make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, float* vel, T* psi, cx<T>* work,
+                              hipStream_t s, hipEvent_t* ev);
+    static hipError_t tau_table(T* tau, int64_t ntau, int n, double box, double amp_growth2, double gamma,
+                                double n_s, hipStream_t s);
+    // bytes of the fused path's workspace (three half spectra without the
+    // k2 = N/2 plane) and of the inverse transform's scratch (one full half
+    // spectrum)
+    static size_t fused_work_bytes(int n) { return 3 * (size_t)n * n * (n / 2) * sizeof(cx<T>); }
+    static size_t inverse_work_bytes(int n) { return (size_t)n * n * (n / 2 + 1) * sizeof(cx<T>); }
+};
+
+// Launches the FP64 sigma_8 integral (one work-group) on stream s.
+hipError_t launch_sigma_integral(double lnk_min, double lnk_max, double gamma, double n_s, double radius,
+                                 double* out, hipStream_t s);
+
+}  // namespace gg

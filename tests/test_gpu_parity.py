@@ -1,0 +1,186 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle.
+
+Tolerances: noise bit-exact; FP64 fields 1e-12 relative r.m.s.; FP32 fields
+2e-6 relative r.m.s. (the precision bars of the target); float32 particle
+positions within 1 ulp of the oracle's rounded positions.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2511_10353_amd as gg
+from oracle import cosmology as ocosmo
+from oracle import noise as onoise
+from oracle import pipeline as opipe
+from tests import inputs
+from tests.gpu_util import max_rel, oracle_cosmo, oracle_ic, oracle_noise, rel_rms, say, ulp_diff_f32
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 2e-6, "f64": 1e-12}
+NPDT = {"f32": np.float32, "f64": np.float64}
+
+
+def _plan(n, box, dtype, **kw):
+    say(f"[plan] n={n} box={box} dtype={dtype} {kw}")
+    return gg.Plan(n, box, gg.Cosmo(**kw), dtype=dtype)
+
+
+def test_plan_normalisation_matches_oracle():
+    for dtype in ("f32", "f64"):
+        p = _plan(32, 100.0, dtype)
+        c = oracle_cosmo(p.cosmo)
+        a = ocosmo.amplitude(c)
+        assert abs(p.info["amplitude"] / a - 1.0) < 1e-12
+        assert abs(p.info["velocity_factor"] - ocosmo.velocity_factor(c)) < 1e-12
+        assert p.info["growth"] == 1.0 / 101.0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
+def test_noise_bit_exact_small(n, dtype):
+    p = _plan(n, 100.0, dtype)
+    for seed, stream in ((42, 0), (2**63 + 12345, 7)):
+        got = p.noise(seed, stream_id=stream).cpu().numpy()
+        want = onoise.noise_grid(n, seed, stream, dtype=NPDT[dtype])
+        assert got.tobytes() == want.tobytes()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_noise_bit_exact_256(dtype):
+    p = _plan(256, 500.0, dtype)
+    got = p.noise(42).cpu().numpy()
+    want = oracle_noise(256, 42, dtype)
+    assert got.tobytes() == want.tobytes()
+
+
+def test_noise_bit_exact_sampled_1024():
+    n = 1024
+    p = _plan(n, 2000.0, "f32")
+    w = p.noise(42)
+    cells = inputs.cell_sample(n, 200000, 1)
+    cells = np.concatenate([cells, [0, 1, 2, 3, n ** 3 - 1]])
+    got = w.view(-1)[torch.from_numpy(cells).cuda()].cpu().numpy()
+    want = onoise.noise_cells(cells.astype(np.uint64), 42).astype(np.float32)
+    assert got.tobytes() == want.tobytes()
+    del w
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
+def test_fft_forward(n, dtype):
+    p = _plan(n, 100.0, dtype)
+    x = inputs.real_field(n, 100 + n, NPDT[dtype])
+    got = p.fft3d(torch.from_numpy(x).cuda(), 1).cpu().numpy()
+    want = opipe.forward(x.astype(np.float64))
+    say(f"fwd n={n} {dtype} rel_rms={rel_rms(got, want):.3e} max={max_rel(got, want):.3e}")
+    assert rel_rms(got, want) < (1e-13 if dtype == "f64" else 1e-6)
+    assert max_rel(got, want) < (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
+def test_fft_inverse(n, dtype):
+    p = _plan(n, 100.0, dtype)
+    x = inputs.real_field(n, 200 + n, np.float64)
+    spec = opipe.forward(x).astype(np.complex64 if dtype == "f32" else np.complex128)
+    spec_d = torch.from_numpy(spec).cuda()
+    got = p.fft3d(spec_d, -1).cpu().numpy()
+    want = opipe.inverse(spec.astype(np.complex128), n)
+    say(f"inv n={n} {dtype} rel_rms={rel_rms(got, want):.3e}")
+    assert rel_rms(got, want) < (1e-13 if dtype == "f64" else 1e-6)
+    # the input is left unmodified
+    assert np.array_equal(spec_d.cpu().numpy(), spec)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [16, 64])
+def test_filter(n, dtype):
+    box = 100.0
+    p = _plan(n, box, dtype)
+    c = oracle_cosmo(p.cosmo)
+    w_hat = opipe.forward(onoise.noise_grid(n, 3))
+    spec = torch.from_numpy(w_hat.astype(np.complex64 if dtype == "f32" else np.complex128)).cuda()
+    psi, delta = p.filter(spec, want_delta=True)
+    psi = psi.cpu().numpy()
+    d_want = opipe.density_spectrum(w_hat, n, box, c)
+    assert rel_rms(delta.cpu().numpy(), d_want) < TOL[dtype]
+    for j in range(3):
+        want = opipe.displacement_spectrum(d_want, n, box, j)
+        say(f"filter n={n} {dtype} j={j} rel_rms={rel_rms(psi[j], want):.3e}")
+        assert rel_rms(psi[j], want) < TOL[dtype]
+        assert np.all(psi[j][want == 0] == 0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_zeldovich(dtype):
+    n, box = 32, 100.0
+    p = _plan(n, box, dtype)
+    c = oracle_cosmo(p.cosmo)
+    psi = (inputs.real_field(n, 7, np.float64).reshape(1, n, n, n) * np.array([3.0, 2.0, 5.0]).reshape(3, 1, 1, 1))
+    psi = psi.astype(NPDT[dtype])
+    pos, vel = p.zeldovich(torch.from_numpy(psi).cuda())
+    pos, vel = pos.cpu().numpy(), vel.cpu().numpy()
+    for j in range(3):
+        want_pos = opipe.positions(psi[j], n, box, 0.5, j)
+        assert pos[j].tobytes() == want_pos.tobytes()
+        want_vel = opipe.velocities(psi[j], c)
+        if dtype == "f64":
+            assert vel[j].tobytes() == want_vel.tobytes()
+        else:
+            assert ulp_diff_f32(vel[j], want_vel).max() <= 1
+    assert pos.min() >= 0 and pos.max() < box
+
+
+def _check_ic(n, box, seed, dtype, pos, vel, psi):
+    o_pos, o_vel, o_psi = oracle_ic(n, box, seed, dtype)
+    for j in range(3):
+        e = rel_rms(psi[j], o_psi[j])
+        m = max_rel(psi[j], o_psi[j])
+        ev = rel_rms(vel[j], o_vel[j])
+        ud = ulp_diff_f32(pos[j], o_pos[j])
+        say(f"ic n={n} {dtype} j={j} psi rel_rms={e:.3e} max={m:.3e} vel rel_rms={ev:.3e} "
+            f"pos max_ulp={ud.max()} frac_diff={np.mean(ud > 0):.2e}")
+        assert e < TOL[dtype]
+        assert m < 50 * TOL[dtype]
+        assert ev < max(TOL[dtype], 1e-7)
+        assert ud.max() <= 1
+    assert pos.min() >= 0 and pos.max() < box
+
+
+@pytest.mark.parametrize("n,box,dtype", [(32, 100.0, "f64"), (32, 100.0, "f32"), (64, 100.0, "f32"),
+                                         (256, 500.0, "f32"), (256, 500.0, "f64")])
+def test_make_ic_vs_oracle(n, box, dtype):
+    p = _plan(n, box, dtype)
+    pos, vel, psi = p.make_ic(42, want_psi=True)
+    torch.cuda.synchronize()
+    _check_ic(n, box, 42, dtype, pos.cpu().numpy(), vel.cpu().numpy(), psi.cpu().numpy())
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_make_ic_equals_unfused_chain(dtype):
+    n, box = 64, 100.0
+    p = _plan(n, box, dtype)
+    pos, vel, psi = p.make_ic(9, want_psi=True)
+    w = p.noise(9)
+    spec = p.fft3d(w, 1)
+    psi_spec = p.filter(spec)
+    work = p.workspace()
+    psi2 = torch.stack([p.fft3d(psi_spec[j].contiguous(), -1, work=work) for j in range(3)])
+    pos2, vel2 = p.zeldovich(psi2)
+    a, b = psi.cpu().numpy(), psi2.cpu().numpy()
+    assert rel_rms(a, b) < (1e-13 if dtype == "f64" else 1e-6)
+    assert ulp_diff_f32(pos.cpu().numpy(), pos2.cpu().numpy()).max() <= 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_make_ic_deterministic(dtype):
+    p = _plan(128, 300.0, dtype)
+    work = p.workspace()
+    a = p.make_ic(5, work=work, want_psi=True)
+    b = p.make_ic(5, work=work, want_psi=True)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    c = p.make_ic(6, work=work)
+    assert not torch.equal(a[0], c[0])
