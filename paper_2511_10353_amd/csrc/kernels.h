@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_core.h"
 #include "noise_dev.h"
 
@@ -39,6 +41,14 @@ struct PlanView {
     const cx<T>* tw;        // tw[m] = exp(-2 pi i m / N), m < N
     const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2
 };
+
+// Returns x unchanged but hides its value from the optimiser, so that
+// quantities derived from it inside a loop body are recomputed per iteration
+// instead of being hoisted and kept live across the loop (register pressure).
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 
 // Signed mode index of k in [0, n).
 __device__ __forceinline__ int signed_mode(int k, int n) { return k < (n >> 1) ? k : k - n; }
@@ -60,14 +70,29 @@ __global__ void k_noise(T* __restrict__ w, uint64_t ngroups, uint64_t seed, uint
     }
 }
 
+// Lattice coordinates (m0, m1) of spectrum row r.  Plain rows are r = m0 N + m1;
+// the fused path's blocked rows are r = ((m0 / 8) N + m1) 8 + m0 % 8.
+template <bool BLK>
+__device__ __forceinline__ void row_coords(uint64_t r, int n, int& m0, int& m1) {
+    if constexpr (BLK) {
+        const uint64_t h = r >> 3;
+        m0 = (int)((h / n) * 8 + (r & 7));
+        m1 = (int)(h % n);
+    } else {
+        m0 = (int)(r / n);
+        m1 = (int)(r % n);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P1 / forward axis-2 pass: L real lines of N points (from the noise
 // generator or from memory) -> half spectra k2 in [0, N/2) (+ N/2 if NYQ).
 // The N reals are packed as N/2 complex z[m] = x[2m] + i x[2m+1]; after the
 // N/2-point transform Z, X[k] = E + W_N^k O with E = (Z[k] + conj Z[N/2-k])/2,
 // O = (Z[k] - conj Z[N/2-k])/(2i); X[0] = Re Z0 + Im Z0, X[N/2] = Re Z0 - Im Z0.
+// Output row r of the L rows handled by block b is b L + r (contiguous).
 // ---------------------------------------------------------------------------
-template <typename T, int N, bool NOISE, bool NYQ>
+template <typename T, int N, bool NOISE, bool NYQ, bool BLK>
 __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zfwd(const T* __restrict__ in,
                                                                              cx<T>* __restrict__ out,
                                                                              const cx<T>* __restrict__ tw,
@@ -84,19 +109,24 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zfwd(cons
     const uint64_t line0 = (uint64_t)blockIdx.x * L;
 
     if constexpr (NOISE) {
-        // group q of line cc covers cells 4q..4q+3 = complex slots 2q, 2q+1
+        // group q of a line covers cells 4q..4q+3 = complex slots 2q, 2q+1
         for (int gi = t; gi < L * (N / 4); gi += NT) {
             const int cc = gi % L, q = gi / L;
+            int m0, m1;
+            row_coords<BLK>(line0 + cc, N, m0, m1);
             double d[4];
-            noise_group((line0 + cc) * (N / 4) + q, seed, stream, d);
+            noise_group(((uint64_t)m0 * N + m1) * (N / 4) + q, seed, stream, d);
             lds[lidx<L>(2 * q, cc)] = {(T)d[0], (T)d[1]};
             lds[lidx<L>(2 * q + 1, cc)] = {(T)d[2], (T)d[3]};
         }
     } else {
+        static_assert(!BLK, "real input rows are plain");
         const cx<T>* src = reinterpret_cast<const cx<T>*>(in + line0 * N);
-        for (int fi = t; fi < L * M; fi += NT) {
-            const int cc = fi / M, p = fi % M;
-            lds[lidx<L>(p, cc)] = src[fi];
+        for (int fi = t; fi < L * M / 2; fi += NT) {
+            const int cc = fi / (M / 2), p = 2 * (fi % (M / 2));
+            const cx<T> x0 = src[2 * fi], x1 = src[2 * fi + 1];
+            lds[lidx<L>(p, cc)] = x0;
+            lds[lidx<L>(p + 1, cc)] = x1;
         }
     }
     __syncthreads();
@@ -108,23 +138,29 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zfwd(cons
 #pragma unroll
     for (int i = 0; i < V; ++i) lds[lidx<L>(last_pos<M, -1>(j, i), c)] = v[i];
     __syncthreads();
-    cx<T>* dst = out + line0 * MO;
-    for (int fi = t; fi < L * MO; fi += NT) {
-        const int cc = fi / MO, k = fi % MO;
-        cx<T> x;
+    auto post = [&](int cc, int k) -> cx<T> {
         if (k == 0 || k == M) {
             const cx<T> z0 = lds[lidx<L>(0, cc)];
-            x = {k == 0 ? z0.x + z0.y : z0.x - z0.y, (T)0};
-        } else {
-            const cx<T> a = lds[lidx<L>(k, cc)];
-            const cx<T> bz = lds[lidx<L>(M - k, cc)];
-            const cx<T> b = {bz.x, -bz.y};
-            const cx<T> e = cscale(cadd(a, b), (T)0.5);
-            const cx<T> d = csub(a, b);
-            const cx<T> o = {d.y * (T)0.5, -d.x * (T)0.5};
-            x = cadd(e, cmul(o, tw[k]));
+            return {k == 0 ? z0.x + z0.y : z0.x - z0.y, (T)0};
         }
-        dst[fi] = x;
+        const cx<T> a = lds[lidx<L>(k, cc)];
+        const cx<T> bz = lds[lidx<L>(M - k, cc)];
+        const cx<T> b = {bz.x, -bz.y};
+        const cx<T> e = cscale(cadd(a, b), (T)0.5);
+        const cx<T> d = csub(a, b);
+        const cx<T> o = {d.y * (T)0.5, -d.x * (T)0.5};
+        return cadd(e, cmul(o, tw[k]));
+    };
+    cx<T>* dst = out + line0 * MO;
+    if constexpr (NYQ) {
+        for (int fi = t; fi < L * MO; fi += NT) dst[fi] = post(fi / MO, fi % MO);
+    } else {
+        for (int fi = t; fi < L * M / 2; fi += NT) {
+            const int cc = fi / (M / 2), k = 2 * (fi % (M / 2));
+            const cx<T> x0 = post(cc, k), x1 = post(cc, k + 1);
+            dst[2 * fi] = x0;
+            dst[2 * fi + 1] = x1;
+        }
     }
 }
 
@@ -151,8 +187,9 @@ __device__ __forceinline__ void zel_point(T psi, int m, double cell, double offs
 // packing above run backwards: Z[k] = (X[k] + conj X[M-k]) +
 // i W_N^-k (X[k] - conj X[M-k]) (Z[0] from the real parts of X[0], X[M]),
 // an M-point inverse gives x[2m] + i x[2m+1] (unnormalised).
-// MODE 0: write scale * x to a real field.  MODE 1: Eq. (3) for component
-// blockIdx.y (whose spectrum is multiplied by s_2 = k when ZMUL).
+// MODE 0: write scale * x to a real field (plain rows).  MODE 1: Eq. (3) for
+// component blockIdx.y, whose spectrum is multiplied by s_2 = k for
+// component 2 (rows as given by BLK).
 // ---------------------------------------------------------------------------
 struct ZelArgs {
     float* pos;
@@ -160,7 +197,7 @@ struct ZelArgs {
     void* psi;  // optional displacement output (path type), may be null
 };
 
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, bool BLK>
 __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zinv(
     const cx<T>* __restrict__ in0, const cx<T>* __restrict__ in1, const cx<T>* __restrict__ in2, int istride,
     T* __restrict__ out, T scale, PlanView<T> pv, ZelArgs za) {
@@ -178,13 +215,27 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zinv(
     const cx<T>* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
     const bool zmul = (MODE == 1) && comp == 2;
     const cx<T>* src = in + line0 * istride;
-    for (int fi = t; fi < L * M; fi += NT) {
-        const int cc = fi / M, k = fi % M;
-        cx<T> x = src[(int64_t)cc * istride + k];
-        if (zmul) x = cscale(x, (T)k);
-        lds[lidx<L>(k, cc)] = x;
+    if (istride == M) {
+        for (int fi = t; fi < L * M / 2; fi += NT) {
+            const int cc = fi / (M / 2), k = 2 * (fi % (M / 2));
+            cx<T> x0 = src[2 * fi], x1 = src[2 * fi + 1];
+            if (zmul) {
+                x0 = cscale(x0, (T)k);
+                x1 = cscale(x1, (T)(k + 1));
+            }
+            lds[lidx<L>(k, cc)] = x0;
+            lds[lidx<L>(k + 1, cc)] = x1;
+        }
+        if (t < L) nyq[t] = (T)0;
+    } else {
+        for (int fi = t; fi < L * M; fi += NT) {
+            const int cc = fi / M, k = fi % M;
+            cx<T> x = src[(int64_t)cc * istride + k];
+            if (zmul) x = cscale(x, (T)k);
+            lds[lidx<L>(k, cc)] = x;
+        }
+        if (t < L) nyq[t] = src[(int64_t)t * istride + M].x;
     }
-    if (t < L) nyq[t] = (istride > M) ? src[(int64_t)t * istride + M].x : (T)0;
     __syncthreads();
     cx<T> v[V];
 #pragma unroll
@@ -207,83 +258,134 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zinv(
 #pragma unroll
     for (int i = 0; i < V; ++i) lds[lidx<L>(last_pos<M, 1>(j, i), c)] = v[i];
     __syncthreads();
-    const int n = N;
-    const uint64_t n3 = (uint64_t)n * n * n;
-    for (int fi = t; fi < L * M; fi += NT) {
-        const int cc = fi / M, m = fi % M;
-        const cx<T> z = lds[lidx<L>(m, cc)];
-        const uint64_t line = line0 + cc;
-        const uint64_t cell = line * N + 2 * m;
+    const uint64_t n3 = (uint64_t)N * N * N;
+    // four consecutive reals (two complex slots) per lane
+    for (int fi = t; fi < L * M / 2; fi += NT) {
+        const int cc = fi / (M / 2), m = 2 * (fi % (M / 2));
+        const cx<T> z0 = lds[lidx<L>(m, cc)], z1 = lds[lidx<L>(m + 1, cc)];
+        int m0, m1;
+        row_coords<BLK>(line0 + cc, N, m0, m1);
+        const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * m;
         if constexpr (MODE == 0) {
-            *reinterpret_cast<cx<T>*>(out + cell) = {z.x * scale, z.y * scale};
+            T* o = out + cell;
+            *reinterpret_cast<cx<T>*>(o) = {z0.x * scale, z0.y * scale};
+            *reinterpret_cast<cx<T>*>(o + 2) = {z1.x * scale, z1.y * scale};
         } else {
             const uint64_t off = (uint64_t)comp * n3 + cell;
-            int m0, m1;
-            if (comp == 0) m0 = m1 = (int)(line / N);
-            else if (comp == 1) m0 = m1 = (int)(line % N);
-            else { m0 = 2 * m; m1 = 2 * m + 1; }
-            float p0, p1, u0, u1;
-            zel_point<T>(z.x, m0, pv.cell, pv.offset, pv.box, (T)pv.vfac, p0, u0);
-            zel_point<T>(z.y, m1, pv.cell, pv.offset, pv.box, (T)pv.vfac, p1, u1);
-            *reinterpret_cast<float2*>(za.pos + off) = make_float2(p0, p1);
-            *reinterpret_cast<float2*>(za.vel + off) = make_float2(u0, u1);
-            if (za.psi) *reinterpret_cast<cx<T>*>(static_cast<T*>(za.psi) + off) = z;
+            const T vals[4] = {z0.x, z0.y, z1.x, z1.y};
+            float p[4], u[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int mm = comp == 0 ? m0 : (comp == 1 ? m1 : 2 * m + e);
+                zel_point<T>(vals[e], mm, pv.cell, pv.offset, pv.box, (T)pv.vfac, p[e], u[e]);
+            }
+            *reinterpret_cast<float4*>(za.pos + off) = make_float4(p[0], p[1], p[2], p[3]);
+            *reinterpret_cast<float4*>(za.vel + off) = make_float4(u[0], u[1], u[2], u[3]);
+            if (za.psi) {
+                T* q = static_cast<T*>(za.psi) + off;
+                *reinterpret_cast<cx<T>*>(q) = z0;
+                *reinterpret_cast<cx<T>*>(q + 2) = z1;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Strided passes: transforms of length N along an axis whose elements are
-// pstride apart, for L contiguous columns at a time (one 128-byte row chunk
+// Strided passes: transforms of length N along an axis whose elements lie in
+// separate rows, for L contiguous columns at a time (one 128-byte row chunk
 // per element).  Tile blockIdx.x -> (outer index o, column block).  Element
-// (o, p, col) is at o * ostride + p * pstride + col.
-//   SMODE_FWD / SMODE_INV : src -> dst (may alias), forward / unnormalised inverse
-//   SMODE_XFILT (P3)      : axis 0 with o = k1, col = k2
-//   SMODE_YINV3 (P4)      : axis 1 with o = m0, col = k2
+// (o, p, col) is at obase(o) + poff(p) + col with
+//   obase(o) = (o >> oshift) * ohi + (o & (2^oshift - 1)) * olo
+//   poff(p)  = p * pstride,  or, with PBLK, (p >> 3) * phi + (p & 7) * plo.
+// The blocked forms address the fused path's spectra, stored as
+// [m0 / 8][k1][m0 % 8][k2] so that an axis-0 line touches N/8 far-apart
+// regions of 8 neighbouring rows instead of N (fewer TLB misses).
+//   SMODE_FWD / SMODE_INV : in0 -> out0 (may alias), forward / unnormalised inverse
+//   SMODE_XFILT (P3)      : axis 0, o = k1: in0 -> F (out0), G (out1)
+//   SMODE_YINV3 (P4)      : axis 1, o = m0: F (in0) -> A (out0), G (in1) -> B (out1), C (out2)
+// A thread keeps one line's registers only: where a second transform of the
+// same input is needed, the tile is read again (the re-read is served by the
+// caches) rather than held, which keeps the kernels free of register spills.
 // ---------------------------------------------------------------------------
 enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3 };
 
 template <typename T>
 struct StridedArgs {
-    const cx<T>* src;
-    cx<T>* dst0;
-    cx<T>* dst1;
-    cx<T>* dst2;
-    int64_t ostride;
-    int64_t pstride;
+    const cx<T>* in0;
+    const cx<T>* in1;
+    cx<T>* out0;
+    cx<T>* out1;
+    cx<T>* out2;
+    int64_t ohi, olo;
+    int oshift;
+    int64_t pstride;   // linear row stride (PBLK false)
+    int64_t phi, plo;  // blocked row strides (PBLK true)
     int ncols;
     int ncb;  // column blocks per outer index
 };
 
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(Tile<T>::L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T> a, PlanView<T> pv) {
-    constexpr int L = Tile<T>::L;
+template <typename T, int N, int MODE, int L, bool PBLK>
+__global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T> a, PlanView<T> pv) {
     constexpr int V = PlanInfo<N>::V;
+    constexpr int TPL = PlanInfo<N>::TPL;
     static_assert(PlanInfo<N>::template last_radix<-1>() == PlanInfo<N>::template first_radix<1>(),
                   "inverse plan must start where the forward plan ends");
     __shared__ cx<T> lds[L * N];
     const int t = threadIdx.x;
     const int c = t % L, j = t / L;
     const int o = blockIdx.x / a.ncb;
-    const int col = (blockIdx.x % a.ncb) * L + c;
+    const int col0 = (blockIdx.x % a.ncb) * L;
+    const int col = col0 + c;
     const bool valid = col < a.ncols;
-    const int64_t base = (int64_t)o * a.ostride + col;
+    // wave-uniform tile base; lanes past the last column of a ragged tile
+    // re-read the last valid column (so every per-lane offset is >= 0) and
+    // store nothing
+    const int64_t tile = (int64_t)(o >> a.oshift) * a.ohi + (int64_t)(o & ((1 << a.oshift) - 1)) * a.olo + col0;
+    const int cl = valid ? c : a.ncols - 1 - col0;
+    auto poff = [&](int p) -> int64_t {
+        if constexpr (PBLK) return (int64_t)(p >> 3) * a.phi + (int64_t)(p & 7) * a.plo;
+        else return (int64_t)p * a.pstride;
+    };
+    // Slot i of a layout whose first (or only) stage has radix R sits at row
+    // j + TPL (i / R) + (i % R) N / R.  When the compile-time row part is a
+    // multiple of 8 the address splits into a wave-uniform slot pointer
+    // (scalar registers) plus one 32-bit per-lane byte offset.
+    constexpr bool SPLIT = (TPL % 8 == 0) && (N % 128 == 0);
+    auto lane_bytes = [&](int jj) -> uint32_t {
+        return SPLIT ? (uint32_t)((poff(jj) + cl) * (int64_t)sizeof(cx<T>)) : 0u;
+    };
+    auto at = [&](auto* base, int i, int R, int jj, uint32_t laneb) {
+        const int rowc = TPL * (i / R) + (i % R) * (N / R);
+        using P = decltype(base);
+        if constexpr (SPLIT) {
+            auto* slot = base + (tile + poff(rowc));
+            using B = std::conditional_t<std::is_const_v<std::remove_pointer_t<P>>, const char*, char*>;
+            return reinterpret_cast<P>(reinterpret_cast<B>(slot) + laneb);
+        } else {
+            return base + (tile + cl + poff(jj + rowc));
+        }
+    };
+    constexpr int RF = PlanInfo<N>::template first_radix<-1>();  // forward input layout
+    constexpr int RL = PlanInfo<N>::template last_radix<1>();    // inverse output layout
+    constexpr int RM = PlanInfo<N>::template last_radix<-1>();   // forward output = inverse input
     cx<T> v[V];
 
     if constexpr (MODE == SMODE_FWD || MODE == SMODE_INV) {
         constexpr int DIR = MODE == SMODE_FWD ? -1 : 1;
+        constexpr int RI = DIR < 0 ? RF : RM;
+        constexpr int RO = DIR < 0 ? RM : RL;
+        const uint32_t lb = lane_bytes(j);
 #pragma unroll
-        for (int i = 0; i < V; ++i)
-            v[i] = valid ? a.src[base + (int64_t)first_pos<N, DIR>(j, i) * a.pstride] : cx<T>{0, 0};
+        for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RI, j, lb);
         fft_lines<T, N, L, DIR, 1>(v, lds, pv.tw, c, j);
         if (valid) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) a.dst0[base + (int64_t)last_pos<N, DIR>(j, i) * a.pstride] = v[i];
+            for (int i = 0; i < V; ++i) *at(a.out0, i, RO, j, lb) = v[i];
         }
     } else if constexpr (MODE == SMODE_XFILT) {
+        const uint32_t lb = lane_bytes(j);
 #pragma unroll
-        for (int i = 0; i < V; ++i)
-            v[i] = valid ? a.src[base + (int64_t)first_pos<N, -1>(j, i) * a.pstride] : cx<T>{0, 0};
+        for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
         fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, c, j);
         // Eq. (1)-(2) on the spectrum held in registers (positions = axis-0 modes)
         const int s1 = signed_mode(o, N);
@@ -296,45 +398,62 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N>::TPL) void k_strided(Strid
             const int s0 = signed_mode(k0, N);
             const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
             const bool zero = line_zero || (k0 == N / 2);
-            const T tau = zero ? (T)0 : pv.tau[n2];  // tau[0] = 0 removes the mean
-            const cx<T> it = mul_i(cscale(v[i], tau));
-            g[i] = it;
-            v[i] = cscale(it, (T)s0);
+            const T tau = pv.tau[zero ? 0 : n2];  // tau[0] = 0: mean and Nyquist modes vanish
+            g[i] = mul_i(cscale(v[i], tau));
+            v[i] = cscale(g[i], (T)s0);
         }
-        fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, c, j);
-        if (valid) {
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+            const uint32_t lb2 = lane_bytes(jj);
+            if (valid) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) a.dst0[base + (int64_t)last_pos<N, 1>(j, i) * a.pstride] = v[i];
+                for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb2) = v[i];
+            }
         }
-        fft_lines<T, N, L, 1, 1>(g, lds, pv.tw, c, j);
-        if (valid) {
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            fft_lines<T, N, L, 1, 1>(g, lds, pv.tw, cc, jj);
+            const uint32_t lb2 = lane_bytes(jj);
+            if (valid) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) a.dst1[base + (int64_t)last_pos<N, 1>(j, i) * a.pstride] = g[i];
+                for (int i = 0; i < V; ++i) *at(a.out1, i, RL, jj, lb2) = g[i];
+            }
         }
-    } else {  // SMODE_YINV3: src = F, dst1 = G (read, then C in place), dst0 = A (over F), dst2 = B
+    } else {  // SMODE_YINV3
+        {
+            const uint32_t lb = lane_bytes(j);
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RM, j, lb);
+            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, c, j);
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) *at(a.out0, i, RL, j, lb) = v[i];
+            }
+        }
         cx<T> g[V];
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            const uint32_t lb = lane_bytes(jj);
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-            const int64_t off = base + (int64_t)first_pos<N, 1>(j, i) * a.pstride;
-            v[i] = valid ? a.src[off] : cx<T>{0, 0};
-            g[i] = valid ? a.dst1[off] : cx<T>{0, 0};
+            for (int i = 0; i < V; ++i) {
+                g[i] = *at(a.in1, i, RM, jj, lb);
+                v[i] = cscale(g[i], (T)signed_mode(first_pos<N, 1>(jj, i), N));
+            }
+            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) *at(a.out1, i, RL, jj, lb) = v[i];
+            }
         }
-        fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, c, j);
-        if (valid) {
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            const uint32_t lb = lane_bytes(jj);
+            fft_lines<T, N, L, 1, 1>(g, lds, pv.tw, cc, jj);
+            if (valid) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) a.dst0[base + (int64_t)last_pos<N, 1>(j, i) * a.pstride] = v[i];
-        }
-#pragma unroll
-        for (int i = 0; i < V; ++i) v[i] = cscale(g[i], (T)signed_mode(first_pos<N, 1>(j, i), N));
-        fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, c, j);
-        if (valid) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) a.dst2[base + (int64_t)last_pos<N, 1>(j, i) * a.pstride] = v[i];
-        }
-        fft_lines<T, N, L, 1, 1>(g, lds, pv.tw, c, j);
-        if (valid) {
-#pragma unroll
-            for (int i = 0; i < V; ++i) a.dst1[base + (int64_t)last_pos<N, 1>(j, i) * a.pstride] = g[i];
+                for (int i = 0; i < V; ++i) *at(a.out2, i, RL, jj, lb) = g[i];
+            }
         }
     }
 }

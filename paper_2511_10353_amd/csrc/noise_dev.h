@@ -38,9 +38,10 @@ struct u32x4 {
 __device__ __forceinline__ u32x4 philox4x32_10(u32x4 ctr, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = kPhiloxM0 * ctr.x, hi0 = __umulhi(kPhiloxM0, ctr.x);
-        const uint32_t lo1 = kPhiloxM1 * ctr.z, hi1 = __umulhi(kPhiloxM1, ctr.z);
-        ctr = {hi1 ^ ctr.y ^ k0, lo1, hi0 ^ ctr.w ^ k1, lo0};
+        // one 32x32 -> 64-bit product per multiplier gives both halves
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * ctr.x;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * ctr.z;
+        ctr = {(uint32_t)(p1 >> 32) ^ ctr.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ ctr.w ^ k1, (uint32_t)p0};
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }

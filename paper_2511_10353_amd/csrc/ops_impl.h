@@ -29,13 +29,23 @@ inline unsigned capped_grid(uint64_t work, unsigned block) {
     return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-template <typename T, int N, int MODE>
+template <typename T>
+StridedArgs<T> strided_args(const cx<T>* in0, const cx<T>* in1, cx<T>* out0, cx<T>* out1, cx<T>* out2, int64_t ohi,
+                            int64_t olo, int oshift, int64_t pstride, int64_t phi, int64_t plo, int ncols) {
+    return StridedArgs<T>{in0, in1, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0};
+}
+
+template <typename T, int N, int MODE, bool PBLK = false, int L = Tile<T>::L>
 hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStream_t s) {
-    constexpr int L = Tile<T>::L;
     StridedArgs<T> a = a0;
     a.ncb = (a.ncols + L - 1) / L;
+    // the kernel addresses a tile as uniform pointer + 32-bit per-lane byte
+    // offset (row part of thread j plus a column < L): keep it in range
+    const int jmax = PlanInfo<N>::TPL - 1;
+    const int64_t prow = PBLK ? (int64_t)(jmax >> 3) * a.phi + (int64_t)(jmax & 7) * a.plo : (int64_t)jmax * a.pstride;
+    if (a.ncols < 1 || (prow + L) * (int64_t)sizeof(cx<T>) >= (int64_t)1 << 32) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)(N * a.ncb);
-    k_strided<T, N, MODE><<<grid, L * PlanInfo<N>::TPL, 0, s>>>(a, pv);
+    k_strided<T, N, MODE, L, PBLK><<<grid, L * PlanInfo<N>::TPL, 0, s>>>(a, pv);
     return hipGetLastError();
 }
 
@@ -52,15 +62,16 @@ hipError_t Ops<T>::fft_forward(const PlanView<T>& pv, const T* in, cx<T>* out, h
     return dispatch_n(pv.n, [&](auto nc) -> hipError_t {
         constexpr int N = decltype(nc)::value;
         constexpr int M = N / 2, L = Tile<T>::L;
-        k_zfwd<T, N, false, true><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(in, out, pv.tw, 0, 0);
+        constexpr int64_t R = M + 1;  // row length of the plain half spectrum
+        k_zfwd<T, N, false, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(in, out, pv.tw, 0, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        StridedArgs<T> a{out, out, nullptr, nullptr, (int64_t)N * (M + 1), (int64_t)(M + 1), M + 1, 0};
-        e = launch_strided<T, N, SMODE_FWD>(a, pv, s);
+        // axis 1: o = k0, rows k1;  axis 0: o = k1, rows k0
+        e = launch_strided<T, N, SMODE_FWD>(strided_args<T>(out, nullptr, out, nullptr, nullptr, N * R, 0, 0, R, 0, 0, M + 1),
+                                           pv, s);
         if (e != hipSuccess) return e;
-        a.ostride = M + 1;
-        a.pstride = (int64_t)N * (M + 1);
-        return launch_strided<T, N, SMODE_FWD>(a, pv, s);
+        return launch_strided<T, N, SMODE_FWD>(strided_args<T>(out, nullptr, out, nullptr, nullptr, R, 0, 0, N * R, 0, 0, M + 1),
+                                              pv, s);
     });
 }
 
@@ -69,17 +80,16 @@ hipError_t Ops<T>::fft_inverse(const PlanView<T>& pv, const cx<T>* in, T* out, c
     return dispatch_n(pv.n, [&](auto nc) -> hipError_t {
         constexpr int N = decltype(nc)::value;
         constexpr int M = N / 2, L = Tile<T>::L;
-        StridedArgs<T> a{in, work, nullptr, nullptr, (int64_t)(M + 1), (int64_t)N * (M + 1), M + 1, 0};
-        hipError_t e = launch_strided<T, N, SMODE_INV>(a, pv, s);
+        constexpr int64_t R = M + 1;
+        hipError_t e = launch_strided<T, N, SMODE_INV>(
+            strided_args<T>(in, nullptr, work, nullptr, nullptr, R, 0, 0, N * R, 0, 0, M + 1), pv, s);
         if (e != hipSuccess) return e;
-        a.src = work;
-        a.ostride = (int64_t)N * (M + 1);
-        a.pstride = M + 1;
-        e = launch_strided<T, N, SMODE_INV>(a, pv, s);
+        e = launch_strided<T, N, SMODE_INV>(
+            strided_args<T>(work, nullptr, work, nullptr, nullptr, N * R, 0, 0, R, 0, 0, M + 1), pv, s);
         if (e != hipSuccess) return e;
         const T scale = (T)(1.0 / ((double)N * (double)N * (double)N));
-        k_zinv<T, N, 0><<<dim3(N * N / L, 1), L * PlanInfo<M>::TPL, 0, s>>>(work, work, work, M + 1, out, scale, pv,
-                                                                            ZelArgs{nullptr, nullptr, nullptr});
+        k_zinv<T, N, 0, false><<<dim3(N * N / L, 1), L * PlanInfo<M>::TPL, 0, s>>>(
+            work, work, work, M + 1, out, scale, pv, ZelArgs{nullptr, nullptr, nullptr});
         return hipGetLastError();
     });
 }
@@ -114,21 +124,28 @@ hipError_t Ops<T>::make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, flo
         hipError_t e;
 #define GG_MARK(i) \
     if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) return e;
+        // spectra rows are blocked: row ((m0 / 8) N + k1) 8 + m0 % 8 holds k2 in [0, M)
+        const int64_t H = (int64_t)8 * N * M;  // one m0 / 8 slab
         GG_MARK(0)
-        k_zfwd<T, N, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(nullptr, b0, pv.tw, seed, 0u);
+        k_zfwd<T, N, true, false, true><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(nullptr, b0, pv.tw, seed, 0u);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         GG_MARK(1)
-        StridedArgs<T> a{b0, b0, nullptr, nullptr, (int64_t)N * M, (int64_t)M, M, 0};
-        if ((e = launch_strided<T, N, SMODE_FWD>(a, pv, s)) != hipSuccess) return e;
+        // P2: axis 1, o = m0
+        e = launch_strided<T, N, SMODE_FWD>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
+                                           pv, s);
+        if (e != hipSuccess) return e;
         GG_MARK(2)
-        a = StridedArgs<T>{b0, b0, b1, nullptr, (int64_t)M, (int64_t)N * M, M, 0};
-        if ((e = launch_strided<T, N, SMODE_XFILT>(a, pv, s)) != hipSuccess) return e;
+        // P3: axis 0, o = k1; W~ (b0) -> F (b1), G (b2)
+        e = launch_strided<T, N, SMODE_XFILT, true>(strided_args<T>(b0, nullptr, b1, b2, nullptr, 8 * M, 0, 0, 0, H, M, M),
+                                                   pv, s);
+        if (e != hipSuccess) return e;
         GG_MARK(3)
-        a = StridedArgs<T>{b0, b0, b1, b2, (int64_t)N * M, (int64_t)M, M, 0};
-        if ((e = launch_strided<T, N, SMODE_YINV3>(a, pv, s)) != hipSuccess) return e;
+        // P4: axis 1, o = m0; F (b1) -> A (b1), G (b2) -> B (b0), C (b2)
+        e = launch_strided<T, N, SMODE_YINV3>(strided_args<T>(b1, b2, b1, b0, b2, H, M, 3, 8 * M, 0, 0, M), pv, s);
+        if (e != hipSuccess) return e;
         GG_MARK(4)
-        k_zinv<T, N, 1><<<dim3(N * N / L, 3), L * PlanInfo<M>::TPL, 0, s>>>(b0, b2, b1, M, nullptr, (T)1, pv,
-                                                                            ZelArgs{pos, vel, psi});
+        k_zinv<T, N, 1, true><<<dim3(N * N / L, 3), L * PlanInfo<M>::TPL, 0, s>>>(b1, b0, b2, M, nullptr, (T)1, pv,
+                                                                                  ZelArgs{pos, vel, psi});
         if ((e = hipGetLastError()) != hipSuccess) return e;
         GG_MARK(5)
 #undef GG_MARK

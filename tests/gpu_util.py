@@ -39,6 +39,12 @@ def ulp_diff_f32(a, b):
     return np.abs(ia - ib)
 
 
+def periodic_abs_diff(a, b, box):
+    """|a - b| on the periodic interval [0, box)."""
+    d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64))
+    return np.minimum(d, box - d)
+
+
 def oracle_cosmo(c):
     return ocosmo.Cosmology(c.omega_m, c.h, c.n_s, c.sigma8, c.z_init, amp=(c.amp if c.amp > 0 else None))
 
