@@ -1,0 +1,107 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/gg.h declares, its structs have the layout the binding assumes, and
+argument validation rejects bad calls before anything reaches the GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gg.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2511_10353_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2511_10353_amd import build
+        build.build(verbose=False)
+    return binding.lib()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for want in ("gg_noise", "gg_filter", "gg_fft3d", "gg_zeldovich", "gg_make_ic", "gg_plan_create"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    nm = subprocess.run(["nm", "-D", "--defined-only", lib._name], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (gg_\w+)", nm))
+    missing = [n for n in _declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_binding(tmp_path):
+    from paper_2511_10353_amd import binding
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "gg.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(gg_grid), offsetof(gg_grid, box), sizeof(gg_cosmo));
+  printf("%zu %zu %zu\n", offsetof(gg_cosmo, amp), offsetof(gg_cosmo, lattice_offset), sizeof(gg_plan_info));
+  printf("%zu %zu %zu\n", offsetof(gg_plan_info, box), offsetof(gg_plan_info, real_elems),
+         offsetof(gg_plan_info, workspace_bytes));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(binding._Grid), binding._Grid.box.offset, ctypes.sizeof(binding._Cosmo),
+            binding._Cosmo.amp.offset, binding._Cosmo.lattice_offset.offset, ctypes.sizeof(binding._Info),
+            binding._Info.box.offset, binding._Info.real_elems.offset, binding._Info.workspace_bytes.offset]
+    assert got == want
+
+
+def test_status_strings(lib):
+    for code, name in [(0, b"GG_OK"), (1, b"GG_ERR_INVALID_ARG"), (2, b"GG_ERR_UNSUPPORTED_SIZE"),
+                       (3, b"GG_ERR_OUT_OF_MEMORY"), (4, b"GG_ERR_HIP"), (5, b"GG_ERR_INTERNAL")]:
+        assert lib.gg_status_string(code) == name
+
+
+def _create(lib, n=32, box=100.0, dtype=0, **kw):
+    from paper_2511_10353_amd import binding
+    h = ctypes.c_void_p()
+    cosmo = binding.Cosmo(**kw)._c()
+    st = lib.gg_plan_create(ctypes.byref(h), ctypes.byref(binding._Grid(n, box)), ctypes.byref(cosmo), dtype)
+    return st, lib.gg_last_error().decode()
+
+
+@pytest.mark.parametrize("n", [0, 7, 12, 48, 2048, -8])
+def test_unsupported_sizes_rejected(lib, n):
+    st, msg = _create(lib, n=n)
+    assert st == 2 and "power of two" in msg
+
+
+@pytest.mark.parametrize("kw,box,dtype", [({}, 0.0, 0), ({}, -1.0, 0), ({}, float("inf"), 0), ({}, 100.0, 2),
+                                          ({"omega_m": 0.0}, 100.0, 0), ({"h": -0.7}, 100.0, 0),
+                                          ({"z_init": -1.0}, 100.0, 0), ({"sigma8": 0.0}, 100.0, 0),
+                                          ({"amp": -1.0}, 100.0, 0), ({"lattice_offset": float("nan")}, 100.0, 0)])
+def test_bad_arguments_rejected(lib, kw, box, dtype):
+    st, msg = _create(lib, box=box, dtype=dtype, **kw)
+    assert st == 1 and msg
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.gg_plan_create(None, None, None, 0) == 1
+    assert lib.gg_workspace_bytes(None) == 0
+    assert lib.gg_noise(None, 1, 0, None, None) == 1
+    assert lib.gg_fft3d(None, 1, None, None, None, None) == 1
+    assert lib.gg_filter(None, None, None, None, None) == 1
+    assert lib.gg_zeldovich(None, None, None, None, None) == 1
+    assert lib.gg_make_ic(None, 1, None, None, None, None, None) == 1
+    assert lib.gg_plan_query(None, None) == 1
+    assert lib.gg_timing_enable(None, 1) == 1
+    assert lib.gg_plan_destroy(None) == 0
