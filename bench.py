@@ -124,8 +124,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: seeded Philox-4x32-10 white noise, analytic BBKS spectrum",
-        "config": {"workload": f"{args.n}^3 lattice, box {args.box:g} Mpc/h, noise->ICs, FP32 passes "
-                               f"(FP64 noise, sigma8 integral and position sum)",
+        "config": {"workload": f"{args.n}^3 lattice, box {args.box:g} Mpc/h, noise->ICs, FP32 path "
+                               f"(FP64 sigma8 integral and position sum)",
                    "n": args.n, "box_mpc_h": args.box, "seed": 42, "sigma8": 0.8, "z_init": 100.0},
         "hbm_GBs_step": round(f32["bytes_per_step"] / (f32["ms_per_step"] * 1e-3) / 1e9, 1),
         "frac_hbm_step": round(f32["bytes_per_step"] / (f32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

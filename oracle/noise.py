@@ -11,34 +11,37 @@ and its words (w0, w1, w2, w3) feed two Box-Muller pairs:
 cell 4g   <- r_a cos(theta_a),  cell 4g+1 <- r_a sin(theta_a)  from (w0, w1)
 cell 4g+2 <- r_b cos(theta_b),  cell 4g+3 <- r_b sin(theta_b)  from (w2, w3)
 
-``stream`` separates independent fields drawn with the same seed.  The single
-precision field is the binary64 deviate rounded to nearest binary32, so both
-precisions carry the same realisation.
+``stream`` separates independent fields drawn with the same seed.  The
+double precision field uses the binary64 Box-Muller of ``normal.py``; the
+single precision field uses its binary32 variant on the same Philox words, so
+the two precisions carry the same realisation to float32 accuracy (a few
+float32 ulp per cell).
 """
 import numpy as np
 
 from .philox import philox4x32, seed_key
-from .normal import box_muller
+from .normal import box_muller, box_muller_f32
 
 
-def noise_cells(cells, seed, stream=0):
-    """Binary64 noise values for an array of linear cell indices."""
+def noise_cells(cells, seed, stream=0, dtype=np.float64):
+    """Noise values (float64 or float32 arithmetic) for linear cell indices."""
     cells = np.asarray(cells, dtype=np.uint64)
     g = cells >> np.uint64(2)
     lane = (cells & np.uint64(3)).astype(np.int64)
     key = seed_key(seed)
     w0, w1, w2, w3 = philox4x32(
         (g & np.uint64(0xFFFFFFFF), g >> np.uint64(32), np.uint64(stream), np.uint64(0)), key)
-    ga, gb = box_muller(w0, w1)
-    gc, gd = box_muller(w2, w3)
-    return np.select([lane == 0, lane == 1, lane == 2], [ga, gb, gc], gd)
+    bm = box_muller_f32 if np.dtype(dtype) == np.float32 else box_muller
+    ga, gb = bm(w0, w1)
+    gc, gd = bm(w2, w3)
+    return np.select([lane == 0, lane == 1, lane == 2], [ga, gb, gc], gd).astype(dtype)
 
 
 def noise_grid(n, seed, stream=0, dtype=np.float64, chunk=1 << 22):
-    """The full N^3 noise field, shape (n, n, n), in ``dtype`` (f64 or f32)."""
+    """The full N^3 noise field, shape (n, n, n), computed in ``dtype`` (f64 or f32)."""
     total = n * n * n
     out = np.empty(total, dtype=dtype)
     for start in range(0, total, chunk):
         stop = min(total, start + chunk)
-        out[start:stop] = noise_cells(np.arange(start, stop, dtype=np.uint64), seed, stream)
+        out[start:stop] = noise_cells(np.arange(start, stop, dtype=np.uint64), seed, stream, dtype)
     return out.reshape(n, n, n)

@@ -60,13 +60,13 @@ template <typename T>
 __global__ void k_noise(T* __restrict__ w, uint64_t ngroups, uint64_t seed, uint32_t stream) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
          g += (uint64_t)gridDim.x * blockDim.x) {
-        double d[4];
-        noise_group(g, seed, stream, d);
+        T d[4];
+        noise_group<T>(g, seed, stream, d);
         T* o = w + 4 * g;
-        o[0] = (T)d[0];
-        o[1] = (T)d[1];
-        o[2] = (T)d[2];
-        o[3] = (T)d[3];
+        o[0] = d[0];
+        o[1] = d[1];
+        o[2] = d[2];
+        o[3] = d[3];
     }
 }
 
@@ -114,10 +114,10 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zfwd(cons
             const int cc = gi % L, q = gi / L;
             int m0, m1;
             row_coords<BLK>(line0 + cc, N, m0, m1);
-            double d[4];
-            noise_group(((uint64_t)m0 * N + m1) * (N / 4) + q, seed, stream, d);
-            lds[lidx<L>(2 * q, cc)] = {(T)d[0], (T)d[1]};
-            lds[lidx<L>(2 * q + 1, cc)] = {(T)d[2], (T)d[3]};
+            T d[4];
+            noise_group<T>(((uint64_t)m0 * N + m1) * (N / 4) + q, seed, stream, d);
+            lds[lidx<L>(2 * q, cc)] = {d[0], d[1]};
+            lds[lidx<L>(2 * q + 1, cc)] = {d[2], d[3]};
         }
     } else {
         static_assert(!BLK, "real input rows are plain");

@@ -10,9 +10,10 @@
 // becomes (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1, lo(M0 x0));
 // the key advances by the Weyl constants after each round; 10 rounds.
 //
-// Box-Muller uses only correctly rounded binary64 +, -, *, /, sqrt and exact
-// bit manipulation, in a fixed order with contraction disabled, so that any
-// IEEE binary64 implementation of the same sequence gives the same bits:
+// Box-Muller uses only correctly rounded +, -, *, /, sqrt and exact bit
+// manipulation, in a fixed order with contraction disabled, so that any IEEE
+// implementation of the same sequence gives the same bits.  The double path
+// evaluates it in binary64:
 //   u1 = (w_a + 1) 2^-32, u2 = w_b 2^-32
 //   ln u1 = e LN2 + 2 t P(t^2), u1 = m 2^e, m in [sqrt(1/2), sqrt(2)),
 //           t = (m-1)/(m+1), P = sum_{k<=11} t^(2k)/(2k+1) (Horner)
@@ -20,6 +21,12 @@
 //           reflected about pi/4 by an exact integer subtraction, Taylor
 //           series of cos (to x^16) and sin (to x^17) on [0, pi/4] (Horner
 //           in x^2), coefficients (-1)^k/(2k)! and (-1)^k/(2k+1)!.
+// The float path evaluates the same structure in binary32 with series cut to
+// float32 accuracy (atanh 5, cos 6, sin 5 coefficients); for u1 > sqrt(1/2)
+// (w_a >= 0xB504F333) its t = (u1-1)/(u1+1) is formed from the exact integer
+// d = 2^32 - 1 - w_a as -RN(d)/RN(2^33 - d), otherwise u1 = RN(w_a + 1) 2^-32;
+// RN is one rounding of an integer to float32.  Constants are the float32
+// roundings of the binary64 constants.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -102,12 +109,10 @@ __device__ __forceinline__ void bm_cos_sin(uint32_t w, double& cos_t, double& si
     const double c = pc, s = x * ps;
     const double ca = direct ? c : s;
     const double sa = direct ? s : c;
-    switch (q) {
-        case 0: cos_t = ca; sin_t = sa; break;
-        case 1: cos_t = -sa; sin_t = ca; break;
-        case 2: cos_t = -ca; sin_t = -sa; break;
-        default: cos_t = sa; sin_t = -ca; break;
-    }
+    const double c0 = (q & 1u) ? sa : ca;
+    const double s0 = (q & 1u) ? ca : sa;
+    cos_t = (q == 1u || q == 2u) ? -c0 : c0;
+    sin_t = (q >= 2u) ? -s0 : s0;
 }
 
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& ga, double& gb) {
@@ -120,8 +125,90 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& ga,
     gb = r * s;
 }
 
-// Deviates of cells 4g .. 4g+3.
-__device__ __forceinline__ void noise_group(uint64_t g, uint64_t seed, uint32_t stream, double out[4]) {
+// ---- binary32 variant --------------------------------------------------------
+constexpr float kLn2F = (float)0.6931471805599453;
+constexpr float kTwoPiF = (float)6.283185307179586;
+constexpr float kSqrtHalfF = (float)0.7071067811865476;
+constexpr float kTwoM32F = 0x1p-32f;
+constexpr uint32_t kWordSplit = 0xB504F333u;  // smallest w_a with (w_a + 1) 2^-32 > sqrt(1/2)
+constexpr int kAtanhTermsF = 4;
+constexpr int kCosTermsF = 5;
+constexpr int kSinTermsF = 4;
+constexpr float atanh_coeff_f(int k) { return 1.0f / (float)(2 * k + 1); }
+constexpr float cos_coeff_f(int k) { return ((k & 1) ? -1.0f : 1.0f) / (float)factorial_d(2 * k); }
+constexpr float sin_coeff_f(int k) { return ((k & 1) ? -1.0f : 1.0f) / (float)factorial_d(2 * k + 1); }
+
+__device__ __forceinline__ float bm_log_word_f(uint32_t wa) {
+#pragma clang fp contract(off)
+    // both reductions are formed for every lane (no divergent branch); each
+    // lane divides its own numerator/denominator pair once
+    const bool near_one = wa >= kWordSplit;
+    const uint32_t d = 0xFFFFFFFFu - wa;
+    const float dn = (float)d;  // d < 2^31: one rounding
+    // RN(2^33 - d): 2^33 - d lies in (2^32, 2^33], float spacing 512 there;
+    // round to nearest, ties to even, in integers
+    const uint64_t x = (1ull << 33) - (uint64_t)d;
+    uint32_t qd = (uint32_t)(x >> 9);
+    const uint32_t rem = (uint32_t)x & 511u;
+    qd += (rem > 256u || (rem == 256u && (qd & 1u))) ? 1u : 0u;
+    const float dd = (float)qd * 512.0f;  // qd <= 2^24: exact
+    const float u = (float)(wa + 1u) * kTwoM32F;  // used only when wa < kWordSplit
+    const uint32_t bits = __float_as_uint(u);
+    int ei = (int)((bits >> 23) & 0xFF) - 126;
+    const float f = __uint_as_float((bits & 0x007FFFFFu) | 0x3F000000u);
+    const bool low = f < kSqrtHalfF;
+    const float m = low ? f * 2.0f : f;
+    ei -= low ? 1 : 0;
+    const float num = near_one ? -dn : m - 1.0f;
+    const float den = near_one ? dd : m + 1.0f;
+    const float t = num / den;
+    const float e = near_one ? 0.0f : (float)ei;
+    const float s = t * t;
+    float p = atanh_coeff_f(kAtanhTermsF);
+#pragma unroll
+    for (int k = kAtanhTermsF - 1; k >= 0; --k) p = p * s + atanh_coeff_f(k);
+    const float a = e * kLn2F;
+    const float b = 2.0f * (t * p);
+    return a + b;
+}
+
+__device__ __forceinline__ void bm_cos_sin_f(uint32_t w, float& cos_t, float& sin_t) {
+#pragma clang fp contract(off)
+    const uint32_t q = w >> 30;
+    const uint32_t rho = w & 0x3FFFFFFFu;
+    const bool direct = rho < (1u << 29);
+    const uint32_t n = direct ? rho : (1u << 30) - rho;
+    const float x = ((float)n * kTwoM32F) * kTwoPiF;
+    const float z = x * x;
+    float pc = cos_coeff_f(kCosTermsF);
+#pragma unroll
+    for (int k = kCosTermsF - 1; k >= 0; --k) pc = pc * z + cos_coeff_f(k);
+    float ps = sin_coeff_f(kSinTermsF);
+#pragma unroll
+    for (int k = kSinTermsF - 1; k >= 0; --k) ps = ps * z + sin_coeff_f(k);
+    const float c = pc, s = x * ps;
+    // (cos, sin) of alpha, then the quadrant rotation: q odd swaps the pair,
+    // cos changes sign for q = 1, 2 and sin for q = 2, 3 (exact)
+    const float ca = direct ? c : s;
+    const float sa = direct ? s : c;
+    const float c0 = (q & 1u) ? sa : ca;
+    const float s0 = (q & 1u) ? ca : sa;
+    cos_t = (q == 1u || q == 2u) ? -c0 : c0;
+    sin_t = (q >= 2u) ? -s0 : s0;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& ga, float& gb) {
+#pragma clang fp contract(off)
+    const float r = sqrtf(-2.0f * bm_log_word_f(wa));
+    float c, s;
+    bm_cos_sin_f(wb, c, s);
+    ga = r * c;
+    gb = r * s;
+}
+
+// Deviates of cells 4g .. 4g+3 in the path's arithmetic type.
+template <typename T>
+__device__ __forceinline__ void noise_group(uint64_t g, uint64_t seed, uint32_t stream, T out[4]) {
     const u32x4 w = philox4x32_10({(uint32_t)g, (uint32_t)(g >> 32), stream, 0u}, (uint32_t)seed,
                                   (uint32_t)(seed >> 32));
     box_muller(w.x, w.y, out[0], out[1]);

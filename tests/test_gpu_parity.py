@@ -62,7 +62,7 @@ def test_noise_bit_exact_sampled_1024():
     cells = inputs.cell_sample(n, 200000, 1)
     cells = np.concatenate([cells, [0, 1, 2, 3, n ** 3 - 1]])
     got = w.view(-1)[torch.from_numpy(cells).cuda()].cpu().numpy()
-    want = onoise.noise_cells(cells.astype(np.uint64), 42).astype(np.float32)
+    want = onoise.noise_cells(cells.astype(np.uint64), 42, dtype=np.float32)
     assert got.tobytes() == want.tobytes()
     del w
     torch.cuda.empty_cache()
