@@ -105,6 +105,7 @@ typedef struct {
     size_t real_elems;       /* N^3 */
     size_t spectrum_elems;   /* N N (N/2+1) complex values */
     size_t workspace_bytes;  /* = gg_workspace_bytes(plan) */
+    int32_t chunks;          /* launches per pass of P1-P4 in gg_make_ic (pipelining) */
 } gg_plan_info;
 
 typedef struct gg_plan gg_plan;
@@ -161,7 +162,9 @@ gg_status gg_make_ic(const gg_plan* plan, uint64_t seed, float* pos, float* vel,
  * milliseconds over the recorded calls, and the number of calls; it then
  * clears the records.  While enabled the plan is not safe for concurrent
  * calls.  npass is 5 (noise + forward z; forward y; forward x + filter +
- * inverse x; inverse y; inverse z + particles). */
+ * inverse x; inverse y; inverse z + particles).  Passes 1-4 run as
+ * gg_plan_info.chunks launches each, two passes overlapping on two streams;
+ * their times are summed over those launches. */
 gg_status gg_timing_enable(gg_plan* plan, int on);
 gg_status gg_timing_read(gg_plan* plan, double* ms_per_pass, int npass, int* ncalls);
 

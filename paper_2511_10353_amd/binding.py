@@ -11,7 +11,8 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgg.so")
+# GG_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("GG_LIBRARY") or os.path.join(_PKG, "libgg.so")
 
 GG_OK = 0
 STATUS_NAMES = {0: "GG_OK", 1: "GG_ERR_INVALID_ARG", 2: "GG_ERR_UNSUPPORTED_SIZE",
@@ -41,7 +42,7 @@ class _Info(ctypes.Structure):
                 ("amplitude", ctypes.c_double), ("sigma8_integral", ctypes.c_double),
                 ("growth", ctypes.c_double), ("velocity_factor", ctypes.c_double),
                 ("real_elems", ctypes.c_size_t), ("spectrum_elems", ctypes.c_size_t),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("chunks", ctypes.c_int32)]
 
 
 @dataclasses.dataclass

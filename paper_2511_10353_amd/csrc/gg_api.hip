@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gg.h"
+#include "gg.h"
 #include "kernels.h"
 #include "ops.h"
 
@@ -30,8 +30,10 @@ gg_status fail_hip(hipError_t e, const char* what) {
     return GG_ERR_HIP;
 }
 
-constexpr int kTimingSlots = 256;  // calls recorded per gg_timing_read
+constexpr int kTimingSlots = 64;   // calls recorded per gg_timing_read
 constexpr int kPasses = 5;
+constexpr int kMaxChunks = 8;
+constexpr int kLaunchesMax = 4 * kMaxChunks + 1;  // launches of one gg_make_ic
 
 }  // namespace
 
@@ -45,9 +47,13 @@ struct gg_plan {
     void* tau = nullptr;   // ntau values of the dtype
     int64_t ntau = 0;
     double amplitude = 0, sigma_int = 0, growth = 0, vfac = 0, cell = 0;
+    // pipelined launch of the fused path: auxiliary stream, dependency events
+    int nchunk = 1;
+    hipStream_t aux = nullptr;
+    std::vector<hipEvent_t> sync;  // 2 kMaxChunks + 3
     // timing records
     bool timing = false;
-    std::vector<hipEvent_t> events;  // kTimingSlots * (kPasses + 1)
+    std::vector<hipEvent_t> events;  // kTimingSlots * 2 * kLaunchesMax
     int recorded = 0;
 };
 
@@ -227,9 +233,36 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
             st = fail_hip(e, "tau table");
             break;
         }
+        // pipelining of the fused path: GG_CHUNKS overrides the default chunk count
+        int nc = dtype == GG_F64 ? gg::Ops<double>::max_chunks(p->n) : gg::Ops<float>::max_chunks(p->n);
+        if (const char* env = std::getenv("GG_CHUNKS")) {
+            const int want = std::atoi(env);
+            const int cblocks = (p->n / 2) / (dtype == GG_F64 ? gg::Tile<double>::L : gg::Tile<float>::L);
+            if (want == 1 || (want >= 1 && want <= kMaxChunks && p->n >= 256 && (p->n / 8) % want == 0 &&
+                              cblocks % want == 0))
+                nc = want;
+        }
+        p->nchunk = nc;
+        if (nc > 1) {
+            if ((e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking)) != hipSuccess) {
+                st = fail_hip(e, "hipStreamCreate (auxiliary)");
+                break;
+            }
+            p->sync.resize(2 * kMaxChunks + 3, nullptr);
+            for (auto& ev : p->sync) {
+                if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) break;
+            }
+            if (e != hipSuccess) {
+                st = fail_hip(e, "hipEventCreate (sync)");
+                break;
+            }
+        }
     } while (false);
     cleanup();
     if (st != GG_OK) {
+        for (hipEvent_t ev : p->sync)
+            if (ev) hipEventDestroy(ev);
+        if (p->aux) hipStreamDestroy(p->aux);
         if (p->tw) hipFree(p->tw);
         if (p->tau) hipFree(p->tau);
         delete p;
@@ -246,6 +279,9 @@ gg_status gg_plan_destroy(gg_plan* p) {
     if (cur != p->device) hipSetDevice(p->device);
     hipDeviceSynchronize();
     for (hipEvent_t ev : p->events) hipEventDestroy(ev);
+    for (hipEvent_t ev : p->sync)
+        if (ev) hipEventDestroy(ev);
+    if (p->aux) hipStreamDestroy(p->aux);
     if (p->tw) hipFree(p->tw);
     if (p->tau) hipFree(p->tau);
     if (cur >= 0 && cur != p->device) hipSetDevice(cur);
@@ -265,6 +301,7 @@ gg_status gg_plan_query(const gg_plan* p, gg_plan_info* info) {
     info->real_elems = (size_t)p->n * p->n * p->n;
     info->spectrum_elems = (size_t)p->n * p->n * (p->n / 2 + 1);
     info->workspace_bytes = gg_workspace_bytes(p);
+    info->chunks = p->nchunk;
     return GG_OK;
 }
 
@@ -369,26 +406,29 @@ gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, v
     gg_status st = check_device(pc);
     if (st != GG_OK) return st;
     gg_plan* p = const_cast<gg_plan*>(pc);  // timing records are the plan's only mutable state
-    hipEvent_t* ev = nullptr;
+    gg::ExecCtx x;
+    x.a = static_cast<hipStream_t>(stream);
+    x.b = p->aux;
+    x.sync = p->sync.empty() ? nullptr : p->sync.data();
+    x.nchunk = p->nchunk;
     if (p->timing && p->recorded < kTimingSlots) {
-        ev = &p->events[(size_t)p->recorded * (kPasses + 1)];
+        x.tev = &p->events[(size_t)p->recorded * 2 * kLaunchesMax];
         p->recorded++;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
     if (p->dtype == GG_F64)
         e = gg::Ops<double>::make_ic(view<double>(p), seed, pos, vel, static_cast<double*>(psi_opt),
-                                     static_cast<gg::cx<double>*>(work), s, ev);
+                                     static_cast<gg::cx<double>*>(work), x);
     else
         e = gg::Ops<float>::make_ic(view<float>(p), seed, pos, vel, static_cast<float*>(psi_opt),
-                                    static_cast<gg::cx<float>*>(work), s, ev);
+                                    static_cast<gg::cx<float>*>(work), x);
     return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic launch");
 }
 
 gg_status gg_timing_enable(gg_plan* p, int on) {
     if (!p) return fail(GG_ERR_INVALID_ARG, "null plan");
     if (on && p->events.empty()) {
-        p->events.resize((size_t)kTimingSlots * (kPasses + 1));
+        p->events.resize((size_t)kTimingSlots * 2 * kLaunchesMax);
         for (auto& ev : p->events) {
             hipError_t e = hipEventCreate(&ev);
             if (e != hipSuccess) return fail_hip(e, "hipEventCreate");
@@ -405,15 +445,17 @@ gg_status gg_timing_read(gg_plan* p, double* ms, int npass, int* ncalls) {
     for (int i = 0; i < npass; ++i) ms[i] = 0;
     *ncalls = p->recorded;
     if (p->recorded == 0) return GG_OK;
-    hipError_t e = hipEventSynchronize(p->events[(size_t)(p->recorded - 1) * (kPasses + 1) + kPasses]);
+    const int nc = p->nchunk;
+    const int launches = 4 * nc + 1;
+    hipError_t e = hipEventSynchronize(p->events[(size_t)(p->recorded - 1) * 2 * kLaunchesMax + 2 * launches - 1]);
     if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
     for (int r = 0; r < p->recorded; ++r) {
-        for (int i = 0; i < kPasses; ++i) {
+        const hipEvent_t* ev = &p->events[(size_t)r * 2 * kLaunchesMax];
+        for (int k = 0; k < launches; ++k) {
             float t = 0;
-            e = hipEventElapsedTime(&t, p->events[(size_t)r * (kPasses + 1) + i],
-                                    p->events[(size_t)r * (kPasses + 1) + i + 1]);
+            e = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
             if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
-            ms[i] += t;
+            ms[k / nc < kPasses ? k / nc : kPasses - 1] += t;
         }
     }
     p->recorded = 0;

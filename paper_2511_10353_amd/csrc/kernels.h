@@ -39,7 +39,7 @@ struct PlanView {
     double offset;          // Lagrangian offset in cells
     double vfac;            // a H f
     const cx<T>* tw;        // tw[m] = exp(-2 pi i m / N), m < N
-    const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2
+    const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2, binary64 values rounded to T
 };
 
 // Returns x unchanged but hides its value from the optimiser, so that
@@ -90,15 +90,15 @@ __device__ __forceinline__ void row_coords(uint64_t r, int n, int& m0, int& m1) 
 // The N reals are packed as N/2 complex z[m] = x[2m] + i x[2m+1]; after the
 // N/2-point transform Z, X[k] = E + W_N^k O with E = (Z[k] + conj Z[N/2-k])/2,
 // O = (Z[k] - conj Z[N/2-k])/(2i); X[0] = Re Z0 + Im Z0, X[N/2] = Re Z0 - Im Z0.
-// Output row r of the L rows handled by block b is b L + r (contiguous).
+// Block b handles rows row0 + b L + r, r < L (contiguous).
 // ---------------------------------------------------------------------------
-template <typename T, int N, bool NOISE, bool NYQ, bool BLK>
-__global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zfwd(const T* __restrict__ in,
+template <typename T, int N, bool NOISE, bool NYQ, bool BLK, int L = Tile<T>::L>
+__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(const T* __restrict__ in,
                                                                              cx<T>* __restrict__ out,
                                                                              const cx<T>* __restrict__ tw,
-                                                                             uint64_t seed, uint32_t stream) {
+                                                                             uint64_t seed, uint32_t stream,
+                                                                             uint64_t row0) {
     constexpr int M = N / 2;
-    constexpr int L = Tile<T>::L;
     constexpr int TPL = PlanInfo<M>::TPL;
     constexpr int NT = L * TPL;
     constexpr int V = PlanInfo<M>::V;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zfwd(cons
     __shared__ cx<T> lds[L * M];
     const int t = threadIdx.x;
     const int c = t % L, j = t / L;
-    const uint64_t line0 = (uint64_t)blockIdx.x * L;
+    const uint64_t line0 = row0 + (uint64_t)blockIdx.x * L;
 
     if constexpr (NOISE) {
         // group q of a line covers cells 4q..4q+3 = complex slots 2q, 2q+1
@@ -197,12 +197,11 @@ struct ZelArgs {
     void* psi;  // optional displacement output (path type), may be null
 };
 
-template <typename T, int N, int MODE, bool BLK>
-__global__ __launch_bounds__(Tile<T>::L * PlanInfo<N / 2>::TPL) void k_zinv(
+template <typename T, int N, int MODE, bool BLK, int L = Tile<T>::L>
+__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
     const cx<T>* __restrict__ in0, const cx<T>* __restrict__ in1, const cx<T>* __restrict__ in2, int istride,
     T* __restrict__ out, T scale, PlanView<T> pv, ZelArgs za) {
     constexpr int M = N / 2;
-    constexpr int L = Tile<T>::L;
     constexpr int TPL = PlanInfo<M>::TPL;
     constexpr int NT = L * TPL;
     constexpr int V = PlanInfo<M>::V;
@@ -321,7 +320,9 @@ struct StridedArgs {
     int64_t pstride;   // linear row stride (PBLK false)
     int64_t phi, plo;  // blocked row strides (PBLK true)
     int ncols;
-    int ncb;  // column blocks per outer index
+    int ncb;  // column blocks per outer index in this launch
+    int cb0;  // first column block of this launch
+    int o0;   // first outer index of this launch
 };
 
 template <typename T, int N, int MODE, int L, bool PBLK>
@@ -333,8 +334,8 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
     __shared__ cx<T> lds[L * N];
     const int t = threadIdx.x;
     const int c = t % L, j = t / L;
-    const int o = blockIdx.x / a.ncb;
-    const int col0 = (blockIdx.x % a.ncb) * L;
+    const int o = a.o0 + (int)(blockIdx.x / a.ncb);
+    const int col0 = (a.cb0 + (int)(blockIdx.x % a.ncb)) * L;
     const int col = col0 + c;
     const bool valid = col < a.ncols;
     // wave-uniform tile base; lanes past the last column of a ragged tile
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_filter(const cx<T>* __restrict__ w, cx<T>* __restrict__ psi, cx<T>* __restrict__ delta, int n,
-                         T scale, T kf, const T* __restrict__ tau) {
+                         T scale, T kf, PlanView<T> pv) {
     const int mo = n / 2 + 1;
     const uint64_t total = (uint64_t)n * n * mo;
     for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -475,7 +476,7 @@ __global__ void k_filter(const cx<T>* __restrict__ w, cx<T>* __restrict__ psi, c
         const int s0 = signed_mode(k0, n), s1 = signed_mode(k1, n), s2 = k2;
         const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
         const bool zero = (k0 == n / 2) || (k1 == n / 2) || (k2 == n / 2);
-        const T ts = zero ? (T)0 : tau[n2] * scale;
+        const T ts = pv.tau[zero ? 0 : n2] * scale;
         const cx<T> it = mul_i(cscale(w[idx], ts));
         psi[idx] = cscale(it, (T)s0);
         psi[total + idx] = cscale(it, (T)s1);

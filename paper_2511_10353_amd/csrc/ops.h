@@ -16,6 +16,21 @@ constexpr bool supported_n(int n) {
     return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
 }
 
+// Launch context of the fused path.  With nchunk > 1 and an auxiliary stream,
+// P1/P2 are pipelined over axis-0 slabs and P3/P4 over k2 column chunks: the
+// first pass of each pair runs on the caller's stream, the second on the
+// auxiliary one, each chunk waiting for its producer (events in sync[],
+// 2 nchunk + 3 of them).  Passes with different limits (noise arithmetic vs
+// memory traffic) then share the GPU.  tev (or null): 2 events per launch,
+// launches ordered P1 chunks, P2 chunks, P3 chunks, P4 chunks, P5.
+struct ExecCtx {
+    hipStream_t a = nullptr;
+    hipStream_t b = nullptr;
+    hipEvent_t* sync = nullptr;
+    int nchunk = 1;
+    hipEvent_t* tev = nullptr;
+};
+
 template <typename T>
 struct Ops {
     static hipError_t noise(const PlanView<T>& pv, uint64_t seed, uint32_t stream_id, T* w, hipStream_t s);
@@ -23,9 +38,10 @@ struct Ops {
     static hipError_t fft_inverse(const PlanView<T>& pv, const cx<T>* in, T* out, cx<T>* work, hipStream_t s);
     static hipError_t filter(const PlanView<T>& pv, const cx<T>* w, cx<T>* psi, cx<T>* delta, hipStream_t s);
     static hipError_t zeldovich(const PlanView<T>& pv, const T* psi, float* pos, float* vel, hipStream_t s);
-    // ev: null, or 6 events recorded before P1 and after each of P1..P5
     static hipError_t make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, float* vel, T* psi, cx<T>* work,
-                              hipStream_t s, hipEvent_t* ev);
+                              const ExecCtx& x);
+    // chunk count the fused path can use for lattice n (1 = no pipelining)
+    static int max_chunks(int n);
     static hipError_t tau_table(T* tau, int64_t ntau, int n, double box, double amp_growth2, double gamma,
                                 double n_s, hipStream_t s);
     // bytes of the fused path's workspace (three half spectra without the

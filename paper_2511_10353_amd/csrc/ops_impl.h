@@ -23,6 +23,19 @@ hipError_t dispatch_n(int n, F&& f) {
     }
 }
 
+// Lines per work-group of the fused path's axis-2 passes.  Their rows are
+// contiguous, so L only sets the LDS tile (and with it how many work-groups
+// share a compute unit).
+#ifndef GG_ZLINES
+#define GG_ZLINES 16
+#endif
+template <typename T, int N>
+struct ZLines {
+    static constexpr int L = (GG_ZLINES < Tile<T>::L ? GG_ZLINES : Tile<T>::L) <= (N * N / 8)
+                                 ? (GG_ZLINES < Tile<T>::L ? GG_ZLINES : Tile<T>::L)
+                                 : Tile<T>::L;
+};
+
 inline unsigned capped_grid(uint64_t work, unsigned block) {
     uint64_t g = (work + block - 1) / block;
     const uint64_t cap = 256ull * 64ull;
@@ -32,19 +45,28 @@ inline unsigned capped_grid(uint64_t work, unsigned block) {
 template <typename T>
 StridedArgs<T> strided_args(const cx<T>* in0, const cx<T>* in1, cx<T>* out0, cx<T>* out1, cx<T>* out2, int64_t ohi,
                             int64_t olo, int oshift, int64_t pstride, int64_t phi, int64_t plo, int ncols) {
-    return StridedArgs<T>{in0, in1, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0};
+    return StridedArgs<T>{in0, in1, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0};
 }
 
+// Launches tiles o in [o0, o0 + no) x column blocks [cb0, cb0 + nb) (nb = 0:
+// all column blocks; no = 0: all N outer indices).
 template <typename T, int N, int MODE, bool PBLK = false, int L = Tile<T>::L>
-hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStream_t s) {
+hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStream_t s, int o0 = 0, int no = 0,
+                          int cb0 = 0, int nb = 0) {
     StridedArgs<T> a = a0;
-    a.ncb = (a.ncols + L - 1) / L;
+    const int ncb_all = (a.ncols + L - 1) / L;
+    if (nb == 0) nb = ncb_all;
+    if (no == 0) no = N;
+    if (o0 < 0 || no < 1 || o0 + no > N || cb0 < 0 || nb < 1 || cb0 + nb > ncb_all) return hipErrorInvalidValue;
+    a.ncb = nb;
+    a.cb0 = cb0;
+    a.o0 = o0;
     // the kernel addresses a tile as uniform pointer + 32-bit per-lane byte
     // offset (row part of thread j plus a column < L): keep it in range
     const int jmax = PlanInfo<N>::TPL - 1;
     const int64_t prow = PBLK ? (int64_t)(jmax >> 3) * a.phi + (int64_t)(jmax & 7) * a.plo : (int64_t)jmax * a.pstride;
     if (a.ncols < 1 || (prow + L) * (int64_t)sizeof(cx<T>) >= (int64_t)1 << 32) return hipErrorInvalidValue;
-    const unsigned grid = (unsigned)(N * a.ncb);
+    const unsigned grid = (unsigned)(no * nb);
     k_strided<T, N, MODE, L, PBLK><<<grid, L * PlanInfo<N>::TPL, 0, s>>>(a, pv);
     return hipGetLastError();
 }
@@ -63,7 +85,7 @@ hipError_t Ops<T>::fft_forward(const PlanView<T>& pv, const T* in, cx<T>* out, h
         constexpr int N = decltype(nc)::value;
         constexpr int M = N / 2, L = Tile<T>::L;
         constexpr int64_t R = M + 1;  // row length of the plain half spectrum
-        k_zfwd<T, N, false, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(in, out, pv.tw, 0, 0);
+        k_zfwd<T, N, false, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(in, out, pv.tw, 0, 0, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         // axis 1: o = k0, rows k1;  axis 0: o = k1, rows k0
@@ -100,7 +122,7 @@ hipError_t Ops<T>::filter(const PlanView<T>& pv, const cx<T>* w, cx<T>* psi, cx<
     const uint64_t total = (uint64_t)n * n * (n / 2 + 1);
     const T scale = (T)((double)n * (double)n * (double)n);
     const T kf = (T)(2.0 * kPi / pv.box);
-    k_filter<T><<<capped_grid(total, 256), 256, 0, s>>>(w, psi, delta, n, scale, kf, pv.tau);
+    k_filter<T><<<capped_grid(total, 256), 256, 0, s>>>(w, psi, delta, n, scale, kf, pv);
     return hipGetLastError();
 }
 
@@ -112,43 +134,98 @@ hipError_t Ops<T>::zeldovich(const PlanView<T>& pv, const T* psi, float* pos, fl
 }
 
 template <typename T>
+int Ops<T>::max_chunks(int n) {
+    // axis-0 slabs of whole 8-row groups and k2 chunks of whole column blocks;
+    // measured best at 1024^3: 4 chunks (float), 2 (double)
+    const int slabs = n / 8, cblocks = (n / 2) / Tile<T>::L;
+    const int cap = sizeof(T) == 4 ? 4 : 2;
+    int c = 1;
+    while (c < cap && slabs % (2 * c) == 0 && cblocks % (2 * c) == 0 && n >= 256) c *= 2;
+    return c;
+}
+
+template <typename T>
 hipError_t Ops<T>::make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, float* vel, T* psi, cx<T>* work,
-                           hipStream_t s, hipEvent_t* ev) {
+                           const ExecCtx& x) {
     return dispatch_n(pv.n, [&](auto nc) -> hipError_t {
         constexpr int N = decltype(nc)::value;
-        constexpr int M = N / 2, L = Tile<T>::L;
+        constexpr int M = N / 2;
+        constexpr int LZ = ZLines<T, N>::L;
+        const int NC = (x.b && x.sync) ? x.nchunk : 1;
+        if (NC < 1 || (N / 8) % NC != 0 || ((M + Tile<T>::L - 1) / Tile<T>::L) % NC != 0) return hipErrorInvalidValue;
+        const hipStream_t sa = x.a;
+        const hipStream_t sb = NC > 1 ? x.b : x.a;
         const size_t hsz = (size_t)N * N * M;
         cx<T>* b0 = work;
         cx<T>* b1 = work + hsz;
         cx<T>* b2 = work + 2 * hsz;
-        hipError_t e;
-#define GG_MARK(i) \
-    if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        int launch = 0;
+        auto mark = [&](hipStream_t st, int which) -> hipError_t {
+            return x.tev ? hipEventRecord(x.tev[2 * launch + which], st) : hipSuccess;
+        };
+#define GG_TRY(expr) \
+    if ((e = (expr)) != hipSuccess) return e;
         // spectra rows are blocked: row ((m0 / 8) N + k1) 8 + m0 % 8 holds k2 in [0, M)
         const int64_t H = (int64_t)8 * N * M;  // one m0 / 8 slab
-        GG_MARK(0)
-        k_zfwd<T, N, true, false, true><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(nullptr, b0, pv.tw, seed, 0u);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        GG_MARK(1)
-        // P2: axis 1, o = m0
-        e = launch_strided<T, N, SMODE_FWD>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
-                                           pv, s);
-        if (e != hipSuccess) return e;
-        GG_MARK(2)
-        // P3: axis 0, o = k1; W~ (b0) -> F (b1), G (b2)
-        e = launch_strided<T, N, SMODE_XFILT, true>(strided_args<T>(b0, nullptr, b1, b2, nullptr, 8 * M, 0, 0, 0, H, M, M),
-                                                   pv, s);
-        if (e != hipSuccess) return e;
-        GG_MARK(3)
-        // P4: axis 1, o = m0; F (b1) -> A (b1), G (b2) -> B (b0), C (b2)
-        e = launch_strided<T, N, SMODE_YINV3>(strided_args<T>(b1, b2, b1, b0, b2, H, M, 3, 8 * M, 0, 0, M), pv, s);
-        if (e != hipSuccess) return e;
-        GG_MARK(4)
-        k_zinv<T, N, 1, true><<<dim3(N * N / L, 3), L * PlanInfo<M>::TPL, 0, s>>>(b1, b0, b2, M, nullptr, (T)1, pv,
-                                                                                  ZelArgs{pos, vel, psi});
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        GG_MARK(5)
-#undef GG_MARK
+        const StridedArgs<T> a2 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
+        const StridedArgs<T> a3 = strided_args<T>(b0, nullptr, b1, b2, nullptr, 8 * M, 0, 0, 0, H, M, M);
+        const StridedArgs<T> a4 = strided_args<T>(b1, b2, b1, b0, b2, H, M, 3, 8 * M, 0, 0, M);
+        const int xh = (N / 8) / NC;                           // m0 / 8 values per slab
+        const int nb = ((M + Tile<T>::L - 1) / Tile<T>::L) / NC;  // column blocks per chunk
+        if (NC > 1) {
+            GG_TRY(hipEventRecord(x.sync[0], sa))
+            GG_TRY(hipStreamWaitEvent(sb, x.sync[0], 0))
+        }
+        // P1 on slab s (rows of m0 in [8 xh s, 8 xh (s+1))), then P2 on the same slab
+        for (int s = 0; s < NC; ++s) {
+            launch = s;
+            const uint64_t row0 = (uint64_t)s * xh * 8 * N;
+            const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / LZ);
+            GG_TRY(mark(sa, 0))
+            k_zfwd<T, N, true, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(nullptr, b0, pv.tw, seed, 0u,
+                                                                                         row0);
+            GG_TRY(hipGetLastError())
+            GG_TRY(mark(sa, 1))
+            if (NC > 1) {
+                GG_TRY(hipEventRecord(x.sync[1 + s], sa))
+                GG_TRY(hipStreamWaitEvent(sb, x.sync[1 + s], 0))
+            }
+            launch = NC + s;
+            GG_TRY(mark(sb, 0))
+            GG_TRY((launch_strided<T, N, SMODE_FWD>(a2, pv, sb, 8 * xh * s, 8 * xh)))
+            GG_TRY(mark(sb, 1))
+        }
+        if (NC > 1) {
+            GG_TRY(hipEventRecord(x.sync[NC + 1], sb))
+            GG_TRY(hipStreamWaitEvent(sa, x.sync[NC + 1], 0))
+        }
+        // P3 on k2 chunk q (all k1), then P4 on the same chunk (all m0)
+        for (int q = 0; q < NC; ++q) {
+            launch = 2 * NC + q;
+            GG_TRY(mark(sa, 0))
+            GG_TRY((launch_strided<T, N, SMODE_XFILT, true>(a3, pv, sa, 0, 0, nb * q, nb)))
+            GG_TRY(mark(sa, 1))
+            if (NC > 1) {
+                GG_TRY(hipEventRecord(x.sync[NC + 2 + q], sa))
+                GG_TRY(hipStreamWaitEvent(sb, x.sync[NC + 2 + q], 0))
+            }
+            launch = 3 * NC + q;
+            GG_TRY(mark(sb, 0))
+            GG_TRY((launch_strided<T, N, SMODE_YINV3>(a4, pv, sb, 0, 0, nb * q, nb)))
+            GG_TRY(mark(sb, 1))
+        }
+        if (NC > 1) {
+            GG_TRY(hipEventRecord(x.sync[2 * NC + 2], sb))
+            GG_TRY(hipStreamWaitEvent(sa, x.sync[2 * NC + 2], 0))
+        }
+        launch = 4 * NC;
+        GG_TRY(mark(sa, 0))
+        k_zinv<T, N, 1, true, LZ><<<dim3(N * N / LZ, 3), LZ * PlanInfo<M>::TPL, 0, sa>>>(b1, b0, b2, M, nullptr, (T)1,
+                                                                                        pv, ZelArgs{pos, vel, psi});
+        GG_TRY(hipGetLastError())
+        GG_TRY(mark(sa, 1))
+#undef GG_TRY
         return hipSuccess;
     });
 }

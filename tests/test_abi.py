@@ -51,8 +51,8 @@ def test_struct_layout_matches_binding(tmp_path):
 int main(void) {
   printf("%zu %zu %zu\n", sizeof(gg_grid), offsetof(gg_grid, box), sizeof(gg_cosmo));
   printf("%zu %zu %zu\n", offsetof(gg_cosmo, amp), offsetof(gg_cosmo, lattice_offset), sizeof(gg_plan_info));
-  printf("%zu %zu %zu\n", offsetof(gg_plan_info, box), offsetof(gg_plan_info, real_elems),
-         offsetof(gg_plan_info, workspace_bytes));
+  printf("%zu %zu %zu %zu\n", offsetof(gg_plan_info, box), offsetof(gg_plan_info, real_elems),
+         offsetof(gg_plan_info, workspace_bytes), offsetof(gg_plan_info, chunks));
   return 0;
 }
 ''')
@@ -61,7 +61,8 @@ int main(void) {
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(binding._Grid), binding._Grid.box.offset, ctypes.sizeof(binding._Cosmo),
             binding._Cosmo.amp.offset, binding._Cosmo.lattice_offset.offset, ctypes.sizeof(binding._Info),
-            binding._Info.box.offset, binding._Info.real_elems.offset, binding._Info.workspace_bytes.offset]
+            binding._Info.box.offset, binding._Info.real_elems.offset, binding._Info.workspace_bytes.offset,
+            binding._Info.chunks.offset]
     assert got == want
 
 
