@@ -30,9 +30,9 @@
  *   j N^3 + c (3 N^3 values each for positions and velocities).
  * - Noise: cell c belongs to Philox-4x32-10 group g = c/4 (key = seed,
  *   counter = (g, stream_id, 0)); its four words give two Box-Muller pairs
- *   evaluated in binary64 with a fixed operation sequence, so a cell's value
- *   depends only on (seed, stream_id, c).  The float path stores the binary64
- *   deviate rounded to nearest float.
+ *   evaluated with a fixed operation sequence (binary64 on the double path,
+ *   binary32 on the float path), so a cell's value depends only on
+ *   (seed, stream_id, c).  The two precisions agree to a few float ulp.
  *
  * Memory, streams, errors
  * -----------------------
@@ -46,8 +46,10 @@
  *   returns GG_ERR_INVALID_ARG and launches nothing.  gg_last_error() then
  *   holds a message (per thread).  No call throws across the ABI.
  * - A plan is read-only after gg_plan_create, except for the timing records
- *   of gg_timing_enable; calls on one plan from several streams are safe when
- *   each call has its own work buffer and timing is off.
+ *   of gg_timing_enable.  gg_noise, gg_fft3d, gg_filter and gg_zeldovich on one
+ *   plan may run from several streams (each with its own buffers);
+ *   gg_make_ic uses a stream and events owned by the plan, so two gg_make_ic
+ *   calls on one plan must not be in flight from different host threads.
  */
 #ifndef GG_H
 #define GG_H
@@ -152,7 +154,10 @@ gg_status gg_zeldovich(const gg_plan* plan, const void* psi, float* pos, float* 
 /* The whole path from a seed (stream_id 0): noise, forward transform, filter,
  * three inverse transforms and Eq. (3), as five fused passes.  pos and vel as
  * for gg_zeldovich; psi_opt, if not NULL, receives the three displacement
- * fields (3 R arrays).  work must hold gg_workspace_bytes(plan). */
+ * fields (3 R arrays).  work must hold gg_workspace_bytes(plan).  On large
+ * lattices passes 1/2 and 3/4 are pipelined in chunks over `stream` and a
+ * stream owned by the plan: the call is ordered after earlier work on
+ * `stream`, and later work on `stream` starts after all of it. */
 gg_status gg_make_ic(const gg_plan* plan, uint64_t seed, float* pos, float* vel, void* psi_opt, void* work,
                      void* stream);
 
