@@ -37,11 +37,25 @@ def noise_cells(cells, seed, stream=0, dtype=np.float64):
     return np.select([lane == 0, lane == 1, lane == 2], [ga, gb, gc], gd).astype(dtype)
 
 
-def noise_grid(n, seed, stream=0, dtype=np.float64, chunk=1 << 22):
-    """The full N^3 noise field, shape (n, n, n), computed in ``dtype`` (f64 or f32)."""
+def noise_grid(n, seed, stream=0, dtype=np.float64, chunk=1 << 22, workers=1):
+    """The full N^3 noise field, shape (n, n, n), computed in ``dtype`` (f64 or f32).
+
+    ``workers`` > 1 fills disjoint chunks from a thread pool (numpy releases
+    the interpreter lock inside its array loops); the values do not depend on it.
+    """
     total = n * n * n
     out = np.empty(total, dtype=dtype)
-    for start in range(0, total, chunk):
+
+    def fill(start):
         stop = min(total, start + chunk)
         out[start:stop] = noise_cells(np.arange(start, stop, dtype=np.uint64), seed, stream, dtype)
+
+    starts = range(0, total, chunk)
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(fill, starts))
+    else:
+        for start in starts:
+            fill(start)
     return out.reshape(n, n, n)

@@ -1,0 +1,92 @@
+"""Parity at the measured size: the 1024^3 lattice (box 2000 Mpc/h) in the
+launch configuration bench.py times (fused gg_make_ic, pipelined passes).
+
+Default (fast): the float path against the double path over the whole grid,
+exact mean removal, positions within one float32 ulp at the box scale.
+Opt-in (GG_SLOW=1): both paths against the full FP64 oracle, on the whole grid
+and on a periodic 128^3 sub-box.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2511_10353_amd as gg
+from tests import inputs
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+N, BOX, SEED = 1024, 2000.0, 42
+
+
+def _rel_rms_t(a, b):
+    d = (a.double() - b.double()).pow(2).sum()
+    return float(torch.sqrt(d / b.double().pow(2).sum()))
+
+
+def test_fp32_matches_fp64_at_1024():
+    say(f"[1024] FP64 make_ic")
+    p64 = gg.Plan(N, BOX, gg.Cosmo(), dtype="f64")
+    pos64, vel64, psi64 = p64.make_ic(SEED, want_psi=True)
+    torch.cuda.synchronize()
+    p64.close()
+    torch.cuda.empty_cache()
+    say("[1024] FP32 make_ic")
+    p32 = gg.Plan(N, BOX, gg.Cosmo(), dtype="f32")
+    pos32, vel32, psi32 = p32.make_ic(SEED, want_psi=True)
+    torch.cuda.synchronize()
+    for j in range(3):
+        e = _rel_rms_t(psi32[j], psi64[j])
+        ev = _rel_rms_t(vel32[j], vel64[j])
+        rms = float(psi64[j].pow(2).mean().sqrt())
+        mean64 = float(psi64[j].mean())
+        d = (pos32[j].double() - pos64[j].double()).abs()
+        dper = torch.minimum(d, BOX - d)
+        say(f"[1024] j={j} psi rel_rms f32 vs f64 = {e:.3e}  vel {ev:.3e}  rms psi {rms:.4f} Mpc/h  "
+            f"mean/rms {mean64 / rms:.2e}  max |dpos| {float(dper.max()):.3e}")
+        assert e < 2e-6 and ev < 2e-6
+        assert abs(mean64) < 1e-10 * rms
+        assert float(dper.max()) <= float(np.spacing(np.float32(BOX)))
+    assert float(pos32.min()) >= 0 and float(pos32.max()) < BOX
+    del pos64, vel64, psi64, pos32, vel32, psi32
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_1024_against_fp64_oracle():
+    from oracle import cosmology as ocosmo
+    from oracle import noise as onoise
+    from oracle import pipeline as opipe
+    workers = min(16, os.cpu_count() or 1)
+    c = ocosmo.Cosmology()
+    origin = inputs.subbox_origin(N, 42)
+    idx = [np.arange(o, o + 128) % N for o in origin]
+    results = {}
+    for dtype in ("f64", "f32"):
+        say(f"[1024 oracle] GPU {dtype}")
+        p = gg.Plan(N, BOX, gg.Cosmo(), dtype=dtype)
+        _, _, psi = p.make_ic(SEED, want_psi=True)
+        torch.cuda.synchronize()
+        p.close()
+        say(f"[1024 oracle] oracle noise {dtype} ({workers} threads)")
+        w = onoise.noise_grid(N, SEED, dtype=np.float32 if dtype == "f32" else np.float64, workers=workers)
+        w_hat = opipe.forward(w.astype(np.float64), workers=workers)
+        del w
+        d_hat = opipe.density_spectrum(w_hat, N, BOX, c)
+        del w_hat
+        for j in range(3):
+            want = opipe.inverse(opipe.displacement_spectrum(d_hat, N, BOX, j), N, workers=workers)
+            got = psi[j].cpu().numpy().astype(np.float64)
+            full = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+            sb = np.ix_(*idx)
+            sub = float(np.linalg.norm(got[sb] - want[sb]) / np.linalg.norm(want[sb]))
+            results[(dtype, j)] = (full, sub)
+            say(f"[1024 oracle] {dtype} j={j} rel_rms full grid {full:.3e}  128^3 sub-box at {origin} {sub:.3e}")
+            del want, got
+        del psi, d_hat
+        torch.cuda.empty_cache()
+    for (dtype, j), (full, sub) in results.items():
+        bar = 1e-12 if dtype == "f64" else 2e-6
+        assert full < bar and sub < bar

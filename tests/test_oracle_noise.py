@@ -92,6 +92,7 @@ def test_grid_chunking_and_precision():
     a = noise.noise_grid(16, 9, chunk=1000)
     b = noise.noise_grid(16, 9, chunk=1 << 20)
     assert np.array_equal(a, b)
+    assert np.array_equal(noise.noise_grid(16, 9, chunk=700, workers=4), a)
     f = noise.noise_grid(16, 9, dtype=np.float32)
     assert f.dtype == np.float32
     # the float32 path's deviates are the same realisation to float32 accuracy
