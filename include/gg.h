@@ -161,6 +161,31 @@ gg_status gg_zeldovich(const gg_plan* plan, const void* psi, float* pos, float* 
 gg_status gg_make_ic(const gg_plan* plan, uint64_t seed, float* pos, float* vel, void* psi_opt, void* work,
                      void* stream);
 
+/* The same path with the white noise given instead of generated: w is R in the
+ * plan's dtype.  amp_scale multiplies the displacements (amp_scale^2 scales
+ * the spectrum amplitude A; 1 keeps the plan's).  pos and vel may both be NULL
+ * when psi_opt is given (displacements only).  Used as the forward map of the
+ * adjoint below. */
+gg_status gg_make_ic_from_noise(const gg_plan* plan, const void* w, double amp_scale, float* pos, float* vel,
+                                void* psi_opt, void* work, void* stream);
+
+/* Adjoint of gg_make_ic_from_noise (differentiation, Sec. 2.1 Eq. 1-2 and
+ * Sec. 2.2 Eq. 3 are linear in the noise): given the gradient of a loss with
+ * respect to the displacements (g_psi: 3 R in the dtype), positions (g_pos:
+ * 3 N^3 float) and velocities (g_vel: 3 N^3 float) -- any may be NULL, not all
+ * -- writes d loss/d w to g_w (R in the dtype):
+ *   g_w = amp_scale * sum_j L_j^T g_j,   g_j = g_psi_j + g_pos_j + aHf g_vel_j,
+ * where L_j maps w to psi_j.  L_j is a convolution with a real odd kernel, so
+ * L_j^T = -L_j: the adjoint runs the five passes of the forward in mirror
+ * order (three r2c inputs combined in the axis-0 pass, one c2r output) and
+ * recomputes the transform instead of storing intermediates.  If g_log_amp
+ * (a device double) and psi (the forward's displacements, 3 R) are given, it
+ * also writes d loss/d log A = (1/2) sum g psi (psi scales as sqrt(A)), summed
+ * in FP64 in a fixed order.  work: gg_workspace_bytes(plan). */
+gg_status gg_make_ic_adjoint(const gg_plan* plan, const void* g_psi, const float* g_pos, const float* g_vel,
+                             double amp_scale, const void* psi, double* g_log_amp, void* g_w, void* work,
+                             void* stream);
+
 /* Per-pass timing of gg_make_ic with HIP events recorded on the call's
  * stream.  Enable before the calls to time; gg_timing_read waits for the last
  * recorded call and returns, for each of the npass passes, the summed

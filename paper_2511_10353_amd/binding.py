@@ -73,6 +73,8 @@ _SIGS = {
     "gg_filter": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "gg_zeldovich": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "gg_make_ic": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP]),
+    "gg_make_ic_from_noise": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
+    "gg_make_ic_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
     "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -208,6 +210,47 @@ class Plan:
         _check(lib().gg_make_ic(self._h, int(seed), _ptr(pos), _ptr(vel), _ptr(psi), _ptr(work), _stream()))
         return (pos, vel, psi) if psi is not None else (pos, vel)
 
+    def make_ic_from_noise(self, w, amp_scale=1.0, pos=None, vel=None, psi=None, work=None, particles=True,
+                           want_psi=False):
+        """The path from a given noise field w (N^3, path dtype); amp_scale
+        multiplies the displacements.  Returns (pos, vel[, psi]) or psi."""
+        w = self._need(w, self._real_shape(), self.real_dtype, "w")
+        if particles:
+            pos = self._need(pos, (3,) + self._real_shape(), torch.float32, "pos")
+            vel = self._need(vel, (3,) + self._real_shape(), torch.float32, "vel")
+        else:
+            pos = vel = None
+            want_psi = True
+        if want_psi or psi is not None:
+            psi = self._need(psi, (3,) + self._real_shape(), self.real_dtype, "psi")
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_make_ic_from_noise(self._h, _ptr(w), float(amp_scale), _ptr(pos), _ptr(vel), _ptr(psi),
+                                           _ptr(work), _stream()))
+        if not particles:
+            return psi
+        return (pos, vel, psi) if psi is not None else (pos, vel)
+
+    def make_ic_adjoint(self, g_psi=None, g_pos=None, g_vel=None, amp_scale=1.0, psi=None, g_w=None, work=None,
+                        want_log_amp=False):
+        """d loss/d w (and d loss/d log A if want_log_amp, which needs psi)."""
+        shape3 = (3,) + self._real_shape()
+        if g_psi is not None:
+            g_psi = self._need(g_psi, shape3, self.real_dtype, "g_psi")
+        if g_pos is not None:
+            g_pos = self._need(g_pos, shape3, torch.float32, "g_pos")
+        if g_vel is not None:
+            g_vel = self._need(g_vel, shape3, torch.float32, "g_vel")
+        if psi is not None:
+            psi = self._need(psi, shape3, self.real_dtype, "psi")
+        g_w = self._need(g_w, self._real_shape(), self.real_dtype, "g_w")
+        g_la = torch.empty(1, dtype=torch.float64, device="cuda") if want_log_amp else None
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_make_ic_adjoint(self._h, _ptr(g_psi), _ptr(g_pos), _ptr(g_vel), float(amp_scale), _ptr(psi),
+                                        _ptr(g_la), _ptr(g_w), _ptr(work), _stream()))
+        return (g_w, g_la) if want_log_amp else g_w
+
     def timing_enable(self, on=True):
         _check(lib().gg_timing_enable(self._h, 1 if on else 0))
 
@@ -216,3 +259,43 @@ class Plan:
         calls = ctypes.c_int(0)
         _check(lib().gg_timing_read(self._h, ms, N_PASSES, ctypes.byref(calls)))
         return [ms[i] for i in range(N_PASSES)], calls.value
+
+
+class MakeIC(torch.autograd.Function):
+    """Differentiable noise -> (positions, velocities, displacements).
+
+    forward(w, log_amp, plan): w is the white noise (N^3, path dtype),
+    log_amp a 0-d tensor shifting ln A (displacements scale as exp(log_amp/2)).
+    backward runs the library's adjoint passes (nothing but the forward's
+    displacements is kept between the two).
+    """
+
+    @staticmethod
+    def forward(ctx, w, log_amp, plan):
+        scale = float(torch.exp(0.5 * log_amp.detach().double()))
+        pos, vel, psi = plan.make_ic_from_noise(w.detach().contiguous(), scale, want_psi=True)
+        ctx.plan = plan
+        ctx.scale = scale
+        ctx.log_amp_dtype = log_amp.dtype
+        ctx.set_materialize_grads(False)  # unused outputs pass None, not zeros
+        ctx.save_for_backward(psi)
+        return pos, vel, psi
+
+    @staticmethod
+    def backward(ctx, g_pos, g_vel, g_psi):
+        (psi,) = ctx.saved_tensors
+        plan = ctx.plan
+        if g_pos is None and g_vel is None and g_psi is None:
+            return None, None, None
+        f = lambda t, dt: None if t is None else t.to(dt).contiguous()
+        g_w, g_la = plan.make_ic_adjoint(g_psi=f(g_psi, plan.real_dtype), g_pos=f(g_pos, torch.float32),
+                                         g_vel=f(g_vel, torch.float32), amp_scale=ctx.scale, psi=psi,
+                                         want_log_amp=True)
+        return g_w, g_la.reshape(()).to(ctx.log_amp_dtype), None
+
+
+def make_ic_autograd(plan, w, log_amp=None):
+    """(pos, vel, psi) = MakeIC(w, log_amp); log_amp defaults to 0."""
+    if log_amp is None:
+        log_amp = torch.zeros((), dtype=torch.float64, device=w.device)
+    return MakeIC.apply(w, log_amp, plan)

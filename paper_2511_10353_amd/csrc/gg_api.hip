@@ -71,6 +71,7 @@ gg::PlanView<T> view(const gg_plan* p) {
     v.vfac = p->vfac;
     v.tw = static_cast<const gg::cx<T>*>(p->tw);
     v.tau = static_cast<const T*>(p->tau);
+    v.amp_scale = 1.0;
     return v;
 }
 
@@ -423,6 +424,83 @@ gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, v
         e = gg::Ops<float>::make_ic(view<float>(p), seed, pos, vel, static_cast<float*>(psi_opt),
                                     static_cast<gg::cx<float>*>(work), x);
     return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic launch");
+}
+
+gg_status gg_make_ic_from_noise(const gg_plan* pc, const void* w, double amp_scale, float* pos, float* vel,
+                                void* psi_opt, void* work, void* stream) {
+    if (!pc || !w || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_make_ic_from_noise");
+    if (!pos != !vel) return fail(GG_ERR_INVALID_ARG, "pos and vel must both be given or both be NULL");
+    if (!pos && !psi_opt) return fail(GG_ERR_INVALID_ARG, "nothing to write: give pos/vel or psi");
+    if (!(amp_scale > 0) || !std::isfinite(amp_scale)) return fail(GG_ERR_INVALID_ARG, "amp_scale must be > 0");
+    if (!aligned(w) || !aligned(work) || (pos && (!aligned(pos) || !aligned(vel))) || (psi_opt && !aligned(psi_opt)))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t n3 = (size_t)pc->n * pc->n * pc->n;
+    const size_t es = elem_size(pc->dtype);
+    const size_t wb = gg_workspace_bytes(pc);
+    if (overlap(w, es * n3, work, wb) || (psi_opt && (overlap(psi_opt, 3 * es * n3, work, wb) ||
+                                                      overlap(psi_opt, 3 * es * n3, w, es * n3))) ||
+        (pos && (overlap(pos, 12 * n3, vel, 12 * n3) || overlap(pos, 12 * n3, work, wb) ||
+                 overlap(vel, 12 * n3, work, wb))))
+        return fail(GG_ERR_INVALID_ARG, "w, pos, vel, psi and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    gg_plan* p = const_cast<gg_plan*>(pc);
+    gg::ExecCtx x;
+    x.a = static_cast<hipStream_t>(stream);
+    x.b = p->aux;
+    x.sync = p->sync.empty() ? nullptr : p->sync.data();
+    x.nchunk = p->nchunk;
+    hipError_t e;
+    if (p->dtype == GG_F64) {
+        auto v = view<double>(p);
+        v.amp_scale = amp_scale;
+        e = gg::Ops<double>::make_ic_from_noise(v, static_cast<const double*>(w), pos, vel,
+                                                static_cast<double*>(psi_opt), static_cast<gg::cx<double>*>(work), x);
+    } else {
+        auto v = view<float>(p);
+        v.amp_scale = amp_scale;
+        e = gg::Ops<float>::make_ic_from_noise(v, static_cast<const float*>(w), pos, vel, static_cast<float*>(psi_opt),
+                                               static_cast<gg::cx<float>*>(work), x);
+    }
+    return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic_from_noise launch");
+}
+
+gg_status gg_make_ic_adjoint(const gg_plan* pc, const void* g_psi, const float* g_pos, const float* g_vel,
+                             double amp_scale, const void* psi, double* g_log_amp, void* g_w, void* work,
+                             void* stream) {
+    if (!pc || !g_w || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_make_ic_adjoint");
+    if (!g_psi && !g_pos && !g_vel) return fail(GG_ERR_INVALID_ARG, "no gradient given (g_psi, g_pos, g_vel)");
+    if (g_log_amp && !psi) return fail(GG_ERR_INVALID_ARG, "g_log_amp needs the forward displacements psi");
+    if (!(amp_scale > 0) || !std::isfinite(amp_scale)) return fail(GG_ERR_INVALID_ARG, "amp_scale must be > 0");
+    if (!aligned(g_w) || !aligned(work) || (g_psi && !aligned(g_psi)) || (g_pos && !aligned(g_pos)) ||
+        (g_vel && !aligned(g_vel)) || (psi && !aligned(psi)) || (g_log_amp && ((uintptr_t)g_log_amp & 7u)))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned (g_log_amp 8-byte)");
+    const size_t n3 = (size_t)pc->n * pc->n * pc->n;
+    const size_t es = elem_size(pc->dtype);
+    const size_t wb = gg_workspace_bytes(pc);
+    const void* ins[4] = {g_psi, g_pos, g_vel, psi};
+    const size_t inb[4] = {3 * es * n3, 12 * n3, 12 * n3, 3 * es * n3};
+    for (int i = 0; i < 4; ++i)
+        if (ins[i] && (overlap(ins[i], inb[i], work, wb) || overlap(ins[i], inb[i], g_w, es * n3)))
+            return fail(GG_ERR_INVALID_ARG, "inputs must not overlap g_w or work");
+    if (overlap(g_w, es * n3, work, wb)) return fail(GG_ERR_INVALID_ARG, "g_w must not overlap work");
+    if (g_log_amp && overlap(g_log_amp, 8, work, wb)) return fail(GG_ERR_INVALID_ARG, "g_log_amp inside work");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (pc->dtype == GG_F64) {
+        auto v = view<double>(pc);
+        v.amp_scale = amp_scale;
+        e = gg::Ops<double>::adjoint(v, static_cast<const double*>(g_psi), g_pos, g_vel, static_cast<const double*>(psi),
+                                     g_log_amp, static_cast<double*>(g_w), static_cast<gg::cx<double>*>(work), s);
+    } else {
+        auto v = view<float>(pc);
+        v.amp_scale = amp_scale;
+        e = gg::Ops<float>::adjoint(v, static_cast<const float*>(g_psi), g_pos, g_vel, static_cast<const float*>(psi),
+                                    g_log_amp, static_cast<float*>(g_w), static_cast<gg::cx<float>*>(work), s);
+    }
+    return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic_adjoint launch");
 }
 
 gg_status gg_timing_enable(gg_plan* p, int on) {

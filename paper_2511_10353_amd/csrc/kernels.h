@@ -40,6 +40,7 @@ struct PlanView {
     double vfac;            // a H f
     const cx<T>* tw;        // tw[m] = exp(-2 pi i m / N), m < N
     const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2, binary64 values rounded to T
+    double amp_scale;       // displacement scale sqrt(A'/A) (1 for the plan's amplitude)
 };
 
 // Returns x unchanged but hides its value from the optimiser, so that
@@ -92,9 +93,25 @@ __device__ __forceinline__ void row_coords(uint64_t r, int n, int& m0, int& m1) 
 // O = (Z[k] - conj Z[N/2-k])/(2i); X[0] = Re Z0 + Im Z0, X[N/2] = Re Z0 - Im Z0.
 // Block b handles rows row0 + b L + r, r < L (contiguous).
 // ---------------------------------------------------------------------------
-template <typename T, int N, bool NOISE, bool NYQ, bool BLK, int L = Tile<T>::L>
-__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(const T* __restrict__ in,
-                                                                             cx<T>* __restrict__ out,
+// Sources of the real lines of an axis-2 forward pass.
+enum { ZSRC_NOISE = 0, ZSRC_REAL = 1, ZSRC_GRAD = 2 };
+
+// ZSRC_REAL: lines of the real field w (plain rows, line (m0, m1) at
+// (m0 N + m1) N).  ZSRC_GRAD: component blockIdx.y of the adjoint input
+// g = gpsi + gpos + vfac gvel (any of the three may be null; 3 N^3 values each),
+// written to out + blockIdx.y * ostride_comp.
+template <typename T>
+struct ZSrc {
+    const T* w;
+    const T* gpsi;
+    const float* gpos;
+    const float* gvel;
+    double vfac;
+    uint64_t ostride_comp;
+};
+
+template <typename T, int N, int SRC, bool NYQ, bool BLK, int L = Tile<T>::L>
+__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, cx<T>* __restrict__ out,
                                                                              const cx<T>* __restrict__ tw,
                                                                              uint64_t seed, uint32_t stream,
                                                                              uint64_t row0) {
@@ -108,7 +125,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(const T* __re
     const int c = t % L, j = t / L;
     const uint64_t line0 = row0 + (uint64_t)blockIdx.x * L;
 
-    if constexpr (NOISE) {
+    if constexpr (SRC == ZSRC_NOISE) {
         // group q of a line covers cells 4q..4q+3 = complex slots 2q, 2q+1
         for (int gi = t; gi < L * (N / 4); gi += NT) {
             const int cc = gi % L, q = gi / L;
@@ -120,14 +137,41 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(const T* __re
             lds[lidx<L>(2 * q + 1, cc)] = {d[2], d[3]};
         }
     } else {
-        static_assert(!BLK, "real input rows are plain");
-        const cx<T>* src = reinterpret_cast<const cx<T>*>(in + line0 * N);
+        // four consecutive reals (two packed complex slots) per lane
+        const int comp = SRC == ZSRC_GRAD ? (int)blockIdx.y : 0;
+        const uint64_t coff = (uint64_t)comp * N * N * N;
         for (int fi = t; fi < L * M / 2; fi += NT) {
             const int cc = fi / (M / 2), p = 2 * (fi % (M / 2));
-            const cx<T> x0 = src[2 * fi], x1 = src[2 * fi + 1];
+            int m0, m1;
+            row_coords<BLK>(line0 + cc, N, m0, m1);
+            const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * p;
+            cx<T> x0, x1;
+            if constexpr (SRC == ZSRC_REAL) {
+                x0 = *reinterpret_cast<const cx<T>*>(zs.w + cell);
+                x1 = *reinterpret_cast<const cx<T>*>(zs.w + cell + 2);
+            } else {
+                T g[4] = {(T)0, (T)0, (T)0, (T)0};
+                if (zs.gpsi) {
+                    const T* q = zs.gpsi + coff + cell;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) g[e] = q[e];
+                }
+                if (zs.gpos) {
+                    const float4 q = *reinterpret_cast<const float4*>(zs.gpos + coff + cell);
+                    g[0] += (T)q.x; g[1] += (T)q.y; g[2] += (T)q.z; g[3] += (T)q.w;
+                }
+                if (zs.gvel) {
+                    const float4 q = *reinterpret_cast<const float4*>(zs.gvel + coff + cell);
+                    const T vf = (T)zs.vfac;
+                    g[0] += vf * (T)q.x; g[1] += vf * (T)q.y; g[2] += vf * (T)q.z; g[3] += vf * (T)q.w;
+                }
+                x0 = {g[0], g[1]};
+                x1 = {g[2], g[3]};
+            }
             lds[lidx<L>(p, cc)] = x0;
             lds[lidx<L>(p + 1, cc)] = x1;
         }
+        if constexpr (SRC == ZSRC_GRAD) out += (uint64_t)blockIdx.y * zs.ostride_comp;
     }
     __syncthreads();
     cx<T> v[V];
@@ -278,8 +322,8 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
                 const int mm = comp == 0 ? m0 : (comp == 1 ? m1 : 2 * m + e);
                 zel_point<T>(vals[e], mm, pv.cell, pv.offset, pv.box, (T)pv.vfac, p[e], u[e]);
             }
-            *reinterpret_cast<float4*>(za.pos + off) = make_float4(p[0], p[1], p[2], p[3]);
-            *reinterpret_cast<float4*>(za.vel + off) = make_float4(u[0], u[1], u[2], u[3]);
+            if (za.pos) *reinterpret_cast<float4*>(za.pos + off) = make_float4(p[0], p[1], p[2], p[3]);
+            if (za.vel) *reinterpret_cast<float4*>(za.vel + off) = make_float4(u[0], u[1], u[2], u[3]);
             if (za.psi) {
                 T* q = static_cast<T*>(za.psi) + off;
                 *reinterpret_cast<cx<T>*>(q) = z0;
@@ -302,16 +346,20 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
 //   SMODE_FWD / SMODE_INV : in0 -> out0 (may alias), forward / unnormalised inverse
 //   SMODE_XFILT (P3)      : axis 0, o = k1: in0 -> F (out0), G (out1)
 //   SMODE_YINV3 (P4)      : axis 1, o = m0: F (in0) -> A (out0), G (in1) -> B (out1), C (out2)
+//   SMODE_XADJ (A3)       : adjoint of P3 + P4's axis-0 work: forward transforms of
+//                           in0, in1, in2 (component spectra of the gradient),
+//                           S = -i tau (s0 X0 + s1 X1 + s2 X2), inverse -> out0
 // A thread keeps one line's registers only: where a second transform of the
 // same input is needed, the tile is read again (the re-read is served by the
 // caches) rather than held, which keeps the kernels free of register spills.
 // ---------------------------------------------------------------------------
-enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3 };
+enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3, SMODE_XADJ = 4 };
 
 template <typename T>
 struct StridedArgs {
     const cx<T>* in0;
     const cx<T>* in1;
+    const cx<T>* in2;
     cx<T>* out0;
     cx<T>* out1;
     cx<T>* out2;
@@ -399,7 +447,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             const int s0 = signed_mode(k0, N);
             const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
             const bool zero = line_zero || (k0 == N / 2);
-            const T tau = pv.tau[zero ? 0 : n2];  // tau[0] = 0: mean and Nyquist modes vanish
+            const T tau = pv.tau[zero ? 0 : n2] * (T)pv.amp_scale;  // tau[0] = 0: mean and Nyquist vanish
             g[i] = mul_i(cscale(v[i], tau));
             v[i] = cscale(g[i], (T)s0);
         }
@@ -419,6 +467,47 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out1, i, RL, jj, lb2) = g[i];
+            }
+        }
+    } else if constexpr (MODE == SMODE_XADJ) {
+        const int s1 = signed_mode(o, N);
+        const int s2 = col;
+        const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
+        cx<T> acc[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] = {(T)0, (T)0};
+#pragma unroll 1
+        for (int comp = 0; comp < 3; ++comp) {
+            const int jj = opaque(j), cc = opaque(c);
+            const uint32_t lb = lane_bytes(jj);
+            const cx<T>* src = comp == 0 ? a.in0 : (comp == 1 ? a.in1 : a.in2);
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = *at(src, i, RF, jj, lb);
+            fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, cc, jj);
+            const int jk = opaque(jj);
+            const T sc = (T)(comp == 1 ? s1 : s2);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const T s = comp == 0 ? (T)signed_mode(last_pos<N, -1>(jk, i), N) : sc;
+                acc[i] = cadd(acc[i], cscale(v[i], s));
+            }
+        }
+        {
+            const int jj = opaque(j), cc = opaque(c);
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const int k0 = last_pos<N, -1>(jj, i);
+                const int s0 = signed_mode(k0, N);
+                const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
+                const bool zero = line_zero || (k0 == N / 2);
+                const T tau = pv.tau[zero ? 0 : n2] * (T)pv.amp_scale;
+                v[i] = mul_i(cscale(acc[i], -tau));
+            }
+            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+            const uint32_t lb = lane_bytes(jj);
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb) = v[i];
             }
         }
     } else {  // SMODE_YINV3
@@ -457,6 +546,50 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 dot product  sum_c g(c) psi(c) over 3 N^3 values, g the
+// combined adjoint input of ZSrc (gpsi + gpos + vfac gvel): fixed-size blocks
+// write partial sums, one block adds them in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kDotThreads = 256;
+constexpr int kDotBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kDotThreads) void k_dot_partial(ZSrc<T> zs, const T* __restrict__ psi, uint64_t total,
+                                                            double* __restrict__ part) {
+    __shared__ double red[kDotThreads];
+    double acc = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kDotThreads + threadIdx.x; i < total; i += (uint64_t)kDotBlocks * kDotThreads) {
+        double g = 0.0;
+        if (zs.gpsi) g += (double)zs.gpsi[i];
+        if (zs.gpos) g += (double)zs.gpos[i];
+        if (zs.gvel) g += zs.vfac * (double)zs.gvel[i];
+        acc += g * (double)psi[i];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restrict__ part, double scale,
+                                                           double* __restrict__ out) {
+    __shared__ double red[kDotThreads];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < kDotBlocks; i += kDotThreads) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,15 @@ struct Ops {
     static hipError_t zeldovich(const PlanView<T>& pv, const T* psi, float* pos, float* vel, hipStream_t s);
     static hipError_t make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, float* vel, T* psi, cx<T>* work,
                               const ExecCtx& x);
+    // the same path from a given white-noise field w (plain real layout)
+    static hipError_t make_ic_from_noise(const PlanView<T>& pv, const T* w, float* pos, float* vel, T* psi,
+                                         cx<T>* work, const ExecCtx& x);
+    // d loss/d w = sum_j L_j^T g_j with g = gpsi + gpos + vfac gvel, and
+    // optionally d loss/d log A = (1/2) sum g psi (one FP64 value at g_log_amp)
+    static hipError_t adjoint(const PlanView<T>& pv, const T* gpsi, const float* gpos, const float* gvel,
+                              const T* psi, double* g_log_amp, T* gw, cx<T>* work, hipStream_t s);
+    static hipError_t fused_forward(const PlanView<T>& pv, const T* w, uint64_t seed, float* pos, float* vel, T* psi,
+                                    cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)
     static int max_chunks(int n);
     static hipError_t tau_table(T* tau, int64_t ntau, int n, double box, double amp_growth2, double gamma,

@@ -44,8 +44,9 @@ inline unsigned capped_grid(uint64_t work, unsigned block) {
 
 template <typename T>
 StridedArgs<T> strided_args(const cx<T>* in0, const cx<T>* in1, cx<T>* out0, cx<T>* out1, cx<T>* out2, int64_t ohi,
-                            int64_t olo, int oshift, int64_t pstride, int64_t phi, int64_t plo, int ncols) {
-    return StridedArgs<T>{in0, in1, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0};
+                            int64_t olo, int oshift, int64_t pstride, int64_t phi, int64_t plo, int ncols,
+                            const cx<T>* in2 = nullptr) {
+    return StridedArgs<T>{in0, in1, in2, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0};
 }
 
 // Launches tiles o in [o0, o0 + no) x column blocks [cb0, cb0 + nb) (nb = 0:
@@ -85,7 +86,8 @@ hipError_t Ops<T>::fft_forward(const PlanView<T>& pv, const T* in, cx<T>* out, h
         constexpr int N = decltype(nc)::value;
         constexpr int M = N / 2, L = Tile<T>::L;
         constexpr int64_t R = M + 1;  // row length of the plain half spectrum
-        k_zfwd<T, N, false, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(in, out, pv.tw, 0, 0, 0);
+        const ZSrc<T> zs{in, nullptr, nullptr, nullptr, 0.0, 0};
+        k_zfwd<T, N, ZSRC_REAL, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(zs, out, pv.tw, 0, 0, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         // axis 1: o = k0, rows k1;  axis 0: o = k1, rows k0
@@ -147,6 +149,18 @@ int Ops<T>::max_chunks(int n) {
 template <typename T>
 hipError_t Ops<T>::make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, float* vel, T* psi, cx<T>* work,
                            const ExecCtx& x) {
+    return fused_forward(pv, nullptr, seed, pos, vel, psi, work, x);
+}
+
+template <typename T>
+hipError_t Ops<T>::make_ic_from_noise(const PlanView<T>& pv, const T* w, float* pos, float* vel, T* psi, cx<T>* work,
+                                      const ExecCtx& x) {
+    return fused_forward(pv, w, 0, pos, vel, psi, work, x);
+}
+
+template <typename T>
+hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t seed, float* pos, float* vel, T* psi,
+                                 cx<T>* work, const ExecCtx& x) {
     return dispatch_n(pv.n, [&](auto nc) -> hipError_t {
         constexpr int N = decltype(nc)::value;
         constexpr int M = N / 2;
@@ -183,8 +197,15 @@ hipError_t Ops<T>::make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, flo
             const uint64_t row0 = (uint64_t)s * xh * 8 * N;
             const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / LZ);
             GG_TRY(mark(sa, 0))
-            k_zfwd<T, N, true, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(nullptr, b0, pv.tw, seed, 0u,
-                                                                                         row0);
+            if (w) {
+                const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0};
+                k_zfwd<T, N, ZSRC_REAL, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0, 0u,
+                                                                                                  row0);
+            } else {
+                const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0};
+                k_zfwd<T, N, ZSRC_NOISE, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, seed,
+                                                                                                   0u, row0);
+            }
             GG_TRY(hipGetLastError())
             GG_TRY(mark(sa, 1))
             if (NC > 1) {
@@ -225,6 +246,54 @@ hipError_t Ops<T>::make_ic(const PlanView<T>& pv, uint64_t seed, float* pos, flo
                                                                                         pv, ZelArgs{pos, vel, psi});
         GG_TRY(hipGetLastError())
         GG_TRY(mark(sa, 1))
+#undef GG_TRY
+        return hipSuccess;
+    });
+}
+
+template <typename T>
+hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gpos, const float* gvel, const T* psi,
+                           double* g_log_amp, T* gw, cx<T>* work, hipStream_t s) {
+    return dispatch_n(pv.n, [&](auto nc) -> hipError_t {
+        constexpr int N = decltype(nc)::value;
+        constexpr int M = N / 2;
+        constexpr int LZ = ZLines<T, N>::L;
+        const size_t hsz = (size_t)N * N * M;
+        cx<T>* b0 = work;
+        cx<T>* b1 = work + hsz;
+        cx<T>* b2 = work + 2 * hsz;
+        const uint64_t n3 = (uint64_t)N * N * N;
+        const ZSrc<T> zs{nullptr, gpsi, gpos, gvel, pv.vfac, (uint64_t)hsz};
+        hipError_t e;
+#define GG_TRY(expr) \
+    if ((e = (expr)) != hipSuccess) return e;
+        if (g_log_amp && psi) {
+            // d loss / d log A = (1/2) sum g psi (psi scales as sqrt(A)); partial sums in b2
+            double* part = reinterpret_cast<double*>(b2);
+            k_dot_partial<T><<<kDotBlocks, kDotThreads, 0, s>>>(zs, psi, 3 * n3, part);
+            GG_TRY(hipGetLastError())
+            k_dot_final<T><<<1, kDotThreads, 0, s>>>(part, 0.5, g_log_amp);
+            GG_TRY(hipGetLastError())
+        }
+        // A1: axis-2 r2c of the three gradient components -> b0, b1, b2 (blocked rows)
+        k_zfwd<T, N, ZSRC_GRAD, false, true, LZ><<<dim3(N * N / LZ, 3), LZ * PlanInfo<M>::TPL, 0, s>>>(zs, b0, pv.tw,
+                                                                                                      0, 0u, 0);
+        GG_TRY(hipGetLastError())
+        // A2: axis-1 forward of each component
+        const int64_t H = (int64_t)8 * N * M;
+        for (cx<T>* b : {b0, b1, b2})
+            GG_TRY((launch_strided<T, N, SMODE_FWD>(strided_args<T>(b, nullptr, b, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
+                                                    pv, s)))
+        // A3: axis-0 forwards, -i tau sum_j s_j X_j, axis-0 inverse -> b0
+        GG_TRY((launch_strided<T, N, SMODE_XADJ, true>(
+            strided_args<T>(b0, b1, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M, b2), pv, s)))
+        // A4: axis-1 inverse
+        GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
+                                                pv, s)))
+        // A5: axis-2 c2r -> d loss / d W (the 1/N^3 is inside tau)
+        k_zinv<T, N, 0, true, LZ><<<dim3(N * N / LZ, 1), LZ * PlanInfo<M>::TPL, 0, s>>>(b0, b0, b0, M, gw, (T)1, pv,
+                                                                                        ZelArgs{nullptr, nullptr, nullptr});
+        GG_TRY(hipGetLastError())
 #undef GG_TRY
         return hipSuccess;
     });
