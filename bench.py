@@ -110,17 +110,80 @@ def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42):
             "bytes_per_step": sum(nbytes), "chunks": chunks}
 
 
-def cpu_baseline(n=256, box=500.0):
-    """The FP64 oracle, untuned, on the host cores: one full pipeline at n^3."""
+def adjoint_bytes(n, elem, log_amp):
+    """Algorithmic HBM bytes of the adjoint's passes A1-A5 for a gradient given
+    with respect to the displacements only."""
+    n3 = n ** 3
+    spec = n3 * elem
+    out = [3 * n3 * elem + 3 * spec,   # A1: read g_psi, write three spectra
+           6 * spec,                   # A2: read + write three spectra
+           3 * spec + spec,            # A3: read three, write one
+           2 * spec,                   # A4
+           spec + n3 * elem]           # A5: read one spectrum, write g_W
+    if log_amp:
+        out[0] += 3 * n3 * elem        # A1 also reads psi for the log-A dot product
+    return out
+
+
+def time_adjoint(gg, torch, n, box, dtype, steps, warmup, seed=42):
+    """One backward step: d loss/d W and d loss/d log A for loss = <g, psi>
+    with a fixed g (a second displacement field), from a resident psi."""
+    plan = gg.Plan(n, box, gg.Cosmo(), dtype=dtype)
+    work = plan.workspace()
+    w = plan.noise(seed)
+    psi = plan.make_ic_from_noise(w, 1.0, work=work, particles=False)
+    g = plan.make_ic_from_noise(plan.noise(seed + 1, out=w), 1.0, work=work, particles=False)
+    g_w = w
+    for _ in range(warmup):
+        plan.make_ic_adjoint(g_psi=g, psi=psi, g_w=g_w, work=work, want_log_amp=True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        plan.make_ic_adjoint(g_psi=g, psi=psi, g_w=g_w, work=work, want_log_amp=True)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    nbytes = sum(adjoint_bytes(n, 4 if dtype == "f32" else 8, True))
+    del plan, work, w, psi, g, g_w
+    torch.cuda.empty_cache()
+    return {"ms_per_step": round(ms, 4), "cells_per_s": round(n ** 3 / (ms * 1e-3), 1), "dtype": dtype,
+            "bytes_per_step": nbytes, "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "what": "gradient of <g, psi> with respect to the noise and log A (five mirror passes, FP64 dot "
+                    "fused into the first)"}
+
+
+def calibrate_copy(torch, gib=1, reps=3):
+    """A plain streaming kernel of known size for scaling the HBM counters:
+    out = in * 1 over gib GiB of float32 (gib GiB read and gib GiB written
+    per launch)."""
+    count = gib * (1 << 30) // 4
+    src = torch.ones(count, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    return {"calibration": "torch.mul(src, 1.0, out=dst)", "read_bytes": count * 4, "write_bytes": count * 4,
+            "launches": reps}
+
+
+def cpu_baseline(n=256, box=500.0, min_seconds=10.0, max_reps=6):
+    """The FP64 oracle, untuned, on the host cores: full pipelines at n^3,
+    repeated (seeds 42, 43, ...) until about min_seconds of CPU work."""
     import numpy as np  # noqa: F401
     from oracle import cosmology, pipeline
     cores = os.cpu_count() or 1
+    reps = 0
     t0 = time.perf_counter()
-    pipeline.make_ic(n, box, cosmology.Cosmology(), 42, workers=cores)
+    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < min_seconds):
+        pipeline.make_ic(n, box, cosmology.Cosmology(), 42 + reps, workers=cores)
+        reps += 1
     dt = time.perf_counter() - t0
-    return {"value": round(n ** 3 / dt, 1), "unit": "cells/s", "cores": cores, "kind": "oracle",
-            "sample": f"full FP64 oracle pipeline (noise, rfftn, filter, 3 irfftn, particles) on one "
-                      f"{n}^3 lattice, box {box:g} Mpc/h, seed 42; scipy.fft workers={cores}; {dt:.1f} s"}
+    return {"value": round(reps * n ** 3 / dt, 1), "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"full FP64 oracle pipeline (noise, rfftn, filter, 3 irfftn, particles) on {reps} "
+                      f"{n}^3 lattices, box {box:g} Mpc/h, seeds 42..{41 + reps}; scipy.fft workers={cores}; "
+                      f"{dt:.1f} s"}
 
 
 def main():
@@ -133,6 +196,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 4 GiB streaming copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the path holds the whole lattice on a single device "
@@ -142,6 +208,9 @@ def main():
     import torch
     import paper_2511_10353_amd as gg
 
+    if args.calibrate_copy:
+        print(json.dumps(calibrate_copy(torch)), flush=True)
+        return 0
     gg.lib()
     f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup)
     f64 = None
@@ -182,6 +251,8 @@ def main():
         out["fp64"] = {"value": round(f64["cells_per_s"], 1), "unit": "cells/s",
                        "ms_per_step": round(f64["ms_per_step"], 4), "passes": f64["passes"],
                        "fp32_speedup": round(f64["ms_per_step"] / f32["ms_per_step"], 3)}
+    if not args.no_adjoint:
+        out["adjoint"] = time_adjoint(gg, torch, args.n, args.box, "f32", max(args.steps // 2, 1), 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

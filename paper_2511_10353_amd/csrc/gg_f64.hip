@@ -30,6 +30,34 @@ __global__ __launch_bounds__(kSigmaThreads) void k_sigma_integral(double lnk_min
 }
 
 
+constexpr int kDotThreads = 1024;
+
+// out = scale * sum of part[0..count), one work-group, fixed order (eight
+// independent partial sums per thread keep eight loads in flight)
+__global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restrict__ part, uint32_t count,
+                                                           double scale, double* __restrict__ out) {
+    __shared__ double red[kDotThreads];
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    uint32_t i = threadIdx.x;
+    for (; i + 7 * kDotThreads < count; i += 8 * kDotThreads) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += part[i + u * kDotThreads];
+    }
+    for (int u = 0; i < count; i += kDotThreads, ++u) acc[u] += part[i];
+    red[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] * scale;
+}
+
+hipError_t launch_dot_final(const double* part, uint32_t count, double scale, double* out, hipStream_t s) {
+    k_dot_final<<<1, kDotThreads, 0, s>>>(part, count, scale, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_sigma_integral(double lnk_min, double lnk_max, double gamma, double n_s, double radius,
                                  double* out, hipStream_t s) {
     k_sigma_integral<<<1, kSigmaThreads, 0, s>>>(lnk_min, lnk_max, gamma, n_s, radius, out);

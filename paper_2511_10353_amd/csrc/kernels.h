@@ -93,13 +93,35 @@ __device__ __forceinline__ void row_coords(uint64_t r, int n, int& m0, int& m1) 
 // O = (Z[k] - conj Z[N/2-k])/(2i); X[0] = Re Z0 + Im Z0, X[N/2] = Re Z0 - Im Z0.
 // Block b handles rows row0 + b L + r, r < L (contiguous).
 // ---------------------------------------------------------------------------
+// Sum of one double per thread over a work-group of NT threads, written by
+// thread 0 to *out.  Fixed order: butterfly within each wave, then the waves
+// in index order (the result does not depend on scheduling).
+template <int NT>
+__device__ inline void block_sum(double v, double* out) {
+    constexpr int W = NT < 64 ? NT : 64;
+    constexpr int NW = NT / W;
+    __shared__ double wsum[NW];
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    const int t = threadIdx.x;
+    if (t % W == 0) wsum[t / W] = v;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int i = 0; i < NW; ++i) s += wsum[i];
+        *out = s;
+    }
+}
+
 // Sources of the real lines of an axis-2 forward pass.
 enum { ZSRC_NOISE = 0, ZSRC_REAL = 1, ZSRC_GRAD = 2 };
 
 // ZSRC_REAL: lines of the real field w (plain rows, line (m0, m1) at
 // (m0 N + m1) N).  ZSRC_GRAD: component blockIdx.y of the adjoint input
 // g = gpsi + gpos + vfac gvel (any of the three may be null; 3 N^3 values each),
-// written to out + blockIdx.y * ostride_comp.
+// written to out + blockIdx.y * ostride_comp.  If psi is not null, each block
+// also writes sum g psi over its cells (g formed in binary64) to
+// part[blockIdx.y gridDim.x + blockIdx.x], summed in a fixed order.
 template <typename T>
 struct ZSrc {
     const T* w;
@@ -108,6 +130,8 @@ struct ZSrc {
     const float* gvel;
     double vfac;
     uint64_t ostride_comp;
+    const T* psi;
+    double* part;
 };
 
 template <typename T, int N, int SRC, bool NYQ, bool BLK, int L = Tile<T>::L>
@@ -138,6 +162,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
         }
     } else {
         // four consecutive reals (two packed complex slots) per lane
+        double dacc = 0.0;
         const int comp = SRC == ZSRC_GRAD ? (int)blockIdx.y : 0;
         const uint64_t coff = (uint64_t)comp * N * N * N;
         for (int fi = t; fi < L * M / 2; fi += NT) {
@@ -150,20 +175,25 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
                 x0 = *reinterpret_cast<const cx<T>*>(zs.w + cell);
                 x1 = *reinterpret_cast<const cx<T>*>(zs.w + cell + 2);
             } else {
-                T g[4] = {(T)0, (T)0, (T)0, (T)0};
+                T a[4] = {(T)0, (T)0, (T)0, (T)0};
+                float4 b = {0.f, 0.f, 0.f, 0.f}, d = {0.f, 0.f, 0.f, 0.f};
                 if (zs.gpsi) {
                     const T* q = zs.gpsi + coff + cell;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) g[e] = q[e];
+                    for (int e = 0; e < 4; ++e) a[e] = q[e];
                 }
-                if (zs.gpos) {
-                    const float4 q = *reinterpret_cast<const float4*>(zs.gpos + coff + cell);
-                    g[0] += (T)q.x; g[1] += (T)q.y; g[2] += (T)q.z; g[3] += (T)q.w;
-                }
-                if (zs.gvel) {
-                    const float4 q = *reinterpret_cast<const float4*>(zs.gvel + coff + cell);
-                    const T vf = (T)zs.vfac;
-                    g[0] += vf * (T)q.x; g[1] += vf * (T)q.y; g[2] += vf * (T)q.z; g[3] += vf * (T)q.w;
+                if (zs.gpos) b = *reinterpret_cast<const float4*>(zs.gpos + coff + cell);
+                if (zs.gvel) d = *reinterpret_cast<const float4*>(zs.gvel + coff + cell);
+                const float bb[4] = {b.x, b.y, b.z, b.w}, dd[4] = {d.x, d.y, d.z, d.w};
+                T g[4];
+                const T vf = (T)zs.vfac;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) g[e] = a[e] + (T)bb[e] + vf * (T)dd[e];
+                if (zs.psi) {
+                    const T* q = zs.psi + coff + cell;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        dacc += ((double)a[e] + (double)bb[e] + zs.vfac * (double)dd[e]) * (double)q[e];
                 }
                 x0 = {g[0], g[1]};
                 x1 = {g[2], g[3]};
@@ -171,7 +201,10 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
             lds[lidx<L>(p, cc)] = x0;
             lds[lidx<L>(p + 1, cc)] = x1;
         }
-        if constexpr (SRC == ZSRC_GRAD) out += (uint64_t)blockIdx.y * zs.ostride_comp;
+        if constexpr (SRC == ZSRC_GRAD) {
+            out += (uint64_t)blockIdx.y * zs.ostride_comp;
+            if (zs.part) block_sum<NT>(dacc, zs.part + (uint64_t)blockIdx.y * gridDim.x + blockIdx.x);
+        }
     }
     __syncthreads();
     cx<T> v[V];
@@ -546,50 +579,6 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             }
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Deterministic FP64 dot product  sum_c g(c) psi(c) over 3 N^3 values, g the
-// combined adjoint input of ZSrc (gpsi + gpos + vfac gvel): fixed-size blocks
-// write partial sums, one block adds them in a fixed order.
-// ---------------------------------------------------------------------------
-constexpr int kDotThreads = 256;
-constexpr int kDotBlocks = 1024;
-
-template <typename T>
-__global__ __launch_bounds__(kDotThreads) void k_dot_partial(ZSrc<T> zs, const T* __restrict__ psi, uint64_t total,
-                                                            double* __restrict__ part) {
-    __shared__ double red[kDotThreads];
-    double acc = 0.0;
-    for (uint64_t i = (uint64_t)blockIdx.x * kDotThreads + threadIdx.x; i < total; i += (uint64_t)kDotBlocks * kDotThreads) {
-        double g = 0.0;
-        if (zs.gpsi) g += (double)zs.gpsi[i];
-        if (zs.gpos) g += (double)zs.gpos[i];
-        if (zs.gvel) g += zs.vfac * (double)zs.gvel[i];
-        acc += g * (double)psi[i];
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restrict__ part, double scale,
-                                                           double* __restrict__ out) {
-    __shared__ double red[kDotThreads];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < kDotBlocks; i += kDotThreads) acc += part[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
 // ---------------------------------------------------------------------------

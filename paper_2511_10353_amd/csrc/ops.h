@@ -60,6 +60,9 @@ struct Ops {
     static size_t inverse_work_bytes(int n) { return (size_t)n * n * (n / 2 + 1) * sizeof(cx<T>); }
 };
 
+// out[0] = scale * sum of part[0..count) in a fixed order (one work-group).
+hipError_t launch_dot_final(const double* part, uint32_t count, double scale, double* out, hipStream_t s);
+
 // Launches the FP64 sigma_8 integral (one work-group) on stream s.
 hipError_t launch_sigma_integral(double lnk_min, double lnk_max, double gamma, double n_s, double radius,
                                  double* out, hipStream_t s);

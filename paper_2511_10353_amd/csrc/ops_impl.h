@@ -86,7 +86,7 @@ hipError_t Ops<T>::fft_forward(const PlanView<T>& pv, const T* in, cx<T>* out, h
         constexpr int N = decltype(nc)::value;
         constexpr int M = N / 2, L = Tile<T>::L;
         constexpr int64_t R = M + 1;  // row length of the plain half spectrum
-        const ZSrc<T> zs{in, nullptr, nullptr, nullptr, 0.0, 0};
+        const ZSrc<T> zs{in, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
         k_zfwd<T, N, ZSRC_REAL, true, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(zs, out, pv.tw, 0, 0, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -198,11 +198,11 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
             const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / LZ);
             GG_TRY(mark(sa, 0))
             if (w) {
-                const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0};
+                const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
                 k_zfwd<T, N, ZSRC_REAL, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0, 0u,
                                                                                                   row0);
             } else {
-                const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0};
+                const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
                 k_zfwd<T, N, ZSRC_NOISE, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, seed,
                                                                                                    0u, row0);
             }
@@ -262,23 +262,23 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
         cx<T>* b0 = work;
         cx<T>* b1 = work + hsz;
         cx<T>* b2 = work + 2 * hsz;
-        const uint64_t n3 = (uint64_t)N * N * N;
-        const ZSrc<T> zs{nullptr, gpsi, gpos, gvel, pv.vfac, (uint64_t)hsz};
+        // d loss / d log A = (1/2) sum g psi (psi scales as sqrt(A)): A1 leaves one
+        // partial sum per work-group in gw, which A5 overwrites later
+        const bool dot = g_log_amp && psi;
+        const uint32_t nblk = (uint32_t)(N * N / LZ);
+        static_assert(3 * (N * N / LZ) * sizeof(double) <= (size_t)N * N * N * sizeof(T), "partials must fit in gw");
+        double* part = reinterpret_cast<double*>(gw);
+        const ZSrc<T> zs{nullptr, gpsi, gpos, gvel, pv.vfac, (uint64_t)hsz, dot ? psi : nullptr, dot ? part : nullptr};
         hipError_t e;
 #define GG_TRY(expr) \
     if ((e = (expr)) != hipSuccess) return e;
-        if (g_log_amp && psi) {
-            // d loss / d log A = (1/2) sum g psi (psi scales as sqrt(A)); partial sums in b2
-            double* part = reinterpret_cast<double*>(b2);
-            k_dot_partial<T><<<kDotBlocks, kDotThreads, 0, s>>>(zs, psi, 3 * n3, part);
-            GG_TRY(hipGetLastError())
-            k_dot_final<T><<<1, kDotThreads, 0, s>>>(part, 0.5, g_log_amp);
-            GG_TRY(hipGetLastError())
-        }
         // A1: axis-2 r2c of the three gradient components -> b0, b1, b2 (blocked rows)
-        k_zfwd<T, N, ZSRC_GRAD, false, true, LZ><<<dim3(N * N / LZ, 3), LZ * PlanInfo<M>::TPL, 0, s>>>(zs, b0, pv.tw,
-                                                                                                      0, 0u, 0);
+        k_zfwd<T, N, ZSRC_GRAD, false, true, LZ><<<dim3(nblk, 3), LZ * PlanInfo<M>::TPL, 0, s>>>(zs, b0, pv.tw, 0,
+                                                                                                  0u, 0);
         GG_TRY(hipGetLastError())
+        if (dot) {
+            GG_TRY(launch_dot_final(part, 3 * nblk, 0.5, g_log_amp, s))
+        }
         // A2: axis-1 forward of each component
         const int64_t H = (int64_t)8 * N * M;
         for (cx<T>* b : {b0, b1, b2})
