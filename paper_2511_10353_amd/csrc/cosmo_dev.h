@@ -32,23 +32,60 @@ __device__ __forceinline__ double tophat(double x) {
     return 3.0 * (sin(x) - x * cos(x)) / (x * x * x);
 }
 
-// tau[n2] = (L / 2 pi) sqrt(P(k) N^3 / L^3) / (n2 N^3), k = (2 pi / L) sqrt(n2);
-// tau[0] = 0.  Evaluated in binary64 and rounded once to T.
+// tau(x) = (L / 2 pi) sqrt(P(k) N^3 / L^3) / (x N^3), k = (2 pi / L) sqrt(x),
+// for real x > 0 (x = n^2 on the lattice).
+__device__ __forceinline__ double tau_value(double x, double n3, double box, double amp_growth2, double gamma,
+                                            double n_s) {
+    const double k = (2.0 * kPi / box) * sqrt(x);
+    const double t = bbks(k, gamma);
+    const double p = amp_growth2 * pow(k, n_s) * t * t;
+    return (box / (2.0 * kPi)) * sqrt(p * n3 / (box * box * box)) / (x * n3);
+}
+
+// tau[n2] = tau_value(n2), tau[0] = 0.  Evaluated in binary64 and rounded
+// once to T.
 template <typename T>
 __global__ void k_tau(T* __restrict__ tau, int64_t ntau, int n, double box, double amp_growth2, double gamma,
                       double n_s) {
     const double n3 = (double)n * (double)n * (double)n;
-    const double kf = 2.0 * kPi / box;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntau; i += (int64_t)gridDim.x * blockDim.x) {
-        double v = 0.0;
-        if (i > 0) {
-            const double n2 = (double)i;
-            const double k = kf * sqrt(n2);
-            const double t = bbks(k, gamma);
-            const double p = amp_growth2 * pow(k, n_s) * t * t;
-            v = (box / (2.0 * kPi)) * sqrt(p * n3 / (box * box * box)) / (n2 * n3);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntau; i += (int64_t)gridDim.x * blockDim.x)
+        tau[i] = i > 0 ? (T)tau_value((double)i, n3, box, amp_growth2, gamma, n_s) : (T)0;
+}
+
+// Piecewise-cubic form of tau for the single-precision fused passes, small
+// enough (15 KB) to sit in LDS next to a transform tile.  Integer n2 < 2^20
+// maps to segment seg(n2) = 64 sh + (n2 >> sh), sh = max(floor(log2 n2) - 6, 0),
+// and t = (n2 mod 2^sh) / 2^sh in [0, 1): segments below 128 hold single
+// integers (exact values), above that each octave is cut into 64 segments of
+// width 2^sh.  Segment coefficients (c0, c1, c2, c3) interpolate tau(x) at
+// t = 0, 1/3, 2/3, 1 (Newton forward differences in binary64, rounded to
+// float); tau ~ x^-a with a < 2 varies by < 4% over a segment, so the cubic's
+// relative error is below 1e-8, under float rounding.
+constexpr int kTauSeg = 64 * 15;  // n2 < 2^20 covers N <= 1024
+
+template <typename T>  // T: the plan's type (instantiated per translation unit)
+__global__ void k_tauseg(float4* __restrict__ seg, int n, double box, double amp_growth2, double gamma,
+                         double n_s) {
+    const double n3 = (double)n * (double)n * (double)n;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < kTauSeg; s += gridDim.x * blockDim.x) {
+        float4 c = {0.f, 0.f, 0.f, 0.f};
+        if (s < 128) {
+            if (s > 0) c.x = (float)tau_value((double)s, n3, box, amp_growth2, gamma, n_s);
+        } else {
+            const int sh = (s >> 6) - 1;
+            const double base = (double)((s & 63) + 64) * (double)(1 << sh);
+            const double w = (double)(1 << sh);
+            double f[4];
+            for (int i = 0; i < 4; ++i) f[i] = tau_value(base + w * i / 3.0, n3, box, amp_growth2, gamma, n_s);
+            const double d1 = f[1] - f[0];
+            const double d2 = f[2] - 2.0 * f[1] + f[0];
+            const double d3 = f[3] - 3.0 * f[2] + 3.0 * f[1] - f[0];
+            c.x = (float)f[0];
+            c.y = (float)(3.0 * d1 - 1.5 * d2 + d3);
+            c.z = (float)(4.5 * d2 - 4.5 * d3);
+            c.w = (float)(4.5 * d3);
         }
-        tau[i] = (T)v;
+        seg[s] = c;
     }
 }
 

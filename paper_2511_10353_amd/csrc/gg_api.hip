@@ -46,6 +46,7 @@ struct gg_plan {
     void* tw = nullptr;    // N complex values of the dtype
     void* tau = nullptr;   // ntau values of the dtype
     int64_t ntau = 0;
+    void* tauseg = nullptr;  // float plans: kTauSeg float4 (piecewise-cubic tau)
     double amplitude = 0, sigma_int = 0, growth = 0, vfac = 0, cell = 0;
     // pipelined launch of the fused path: auxiliary stream, dependency events
     int nchunk = 1;
@@ -71,6 +72,7 @@ gg::PlanView<T> view(const gg_plan* p) {
     v.vfac = p->vfac;
     v.tw = static_cast<const gg::cx<T>*>(p->tw);
     v.tau = static_cast<const T*>(p->tau);
+    v.tauseg = static_cast<const float4*>(p->tauseg);
     v.amp_scale = 1.0;
     return v;
 }
@@ -185,7 +187,8 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     };
     do {
         if ((e = hipMalloc(&p->tw, 2 * es * p->n)) != hipSuccess ||
-            (e = hipMalloc(&p->tau, es * p->ntau)) != hipSuccess || (e = hipMalloc(&d_sig, sizeof(double))) != hipSuccess) {
+            (e = hipMalloc(&p->tau, es * p->ntau)) != hipSuccess || (e = hipMalloc(&d_sig, sizeof(double))) != hipSuccess ||
+            (dtype == GG_F32 && (e = hipMalloc(&p->tauseg, gg::kTauSeg * sizeof(float4))) != hipSuccess)) {
             st = fail(GG_ERR_OUT_OF_MEMORY, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
             break;
         }
@@ -226,9 +229,11 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
         p->vfac = a * (100.0 * std::sqrt(c.omega_m / std::pow(a, 3.0) + 1.0 - c.omega_m)) * 1.0;
         const double ag2 = p->amplitude * p->growth * p->growth;
         if (dtype == GG_F64)
-            e = gg::Ops<double>::tau_table(static_cast<double*>(p->tau), p->ntau, p->n, p->box, ag2, gamma, c.n_s, s);
+            e = gg::Ops<double>::tau_table(static_cast<double*>(p->tau), p->ntau, nullptr, p->n, p->box, ag2, gamma,
+                                           c.n_s, s);
         else
-            e = gg::Ops<float>::tau_table(static_cast<float*>(p->tau), p->ntau, p->n, p->box, ag2, gamma, c.n_s, s);
+            e = gg::Ops<float>::tau_table(static_cast<float*>(p->tau), p->ntau, static_cast<float4*>(p->tauseg), p->n,
+                                          p->box, ag2, gamma, c.n_s, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             st = fail_hip(e, "tau table");
@@ -266,6 +271,7 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
         if (p->aux) hipStreamDestroy(p->aux);
         if (p->tw) hipFree(p->tw);
         if (p->tau) hipFree(p->tau);
+        if (p->tauseg) hipFree(p->tauseg);
         delete p;
         return st;
     }
@@ -285,6 +291,7 @@ gg_status gg_plan_destroy(gg_plan* p) {
     if (p->aux) hipStreamDestroy(p->aux);
     if (p->tw) hipFree(p->tw);
     if (p->tau) hipFree(p->tau);
+    if (p->tauseg) hipFree(p->tauseg);
     if (cur >= 0 && cur != p->device) hipSetDevice(cur);
     delete p;
     return GG_OK;

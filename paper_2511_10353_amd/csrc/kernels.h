@@ -25,6 +25,7 @@
 
 #include <type_traits>
 
+#include "cosmo_dev.h"
 #include "fft_core.h"
 #include "noise_dev.h"
 
@@ -40,8 +41,46 @@ struct PlanView {
     double vfac;            // a H f
     const cx<T>* tw;        // tw[m] = exp(-2 pi i m / N), m < N
     const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2, binary64 values rounded to T
+    const float4* tauseg;   // piecewise-cubic tau (kTauSeg segments), float plans only
     double amp_scale;       // displacement scale sqrt(A'/A) (1 for the plan's amplitude)
 };
+
+// The filter factor tau(n2) inside the axis-0 passes of the fused path.  The
+// single-precision passes copy the piecewise-cubic table (15 KB) into LDS once
+// per work-group and evaluate it (scattered reads of the full table missed
+// the L1 and loaded L2 with one request per element); double precision reads
+// the exact table.
+template <typename T>
+struct TauLookup {
+    const T* tau;
+    __device__ T operator()(int n2) const { return tau[n2]; }
+};
+
+template <>
+struct TauLookup<float> {
+    const float4* seg;
+    __device__ float operator()(int n2) const {
+        const uint32_t u = (uint32_t)n2;
+        const int e = 31 - __clz(u | 1u);
+        const int sh = e > 6 ? e - 6 : 0;
+        const float4 c = seg[(sh << 6) + (u >> sh)];
+        const float t = (float)(u & ((1u << sh) - 1u)) * __int_as_float((127 - sh) << 23);
+        return fmaf(t, fmaf(t, fmaf(t, c.w, c.z), c.y), c.x);
+    }
+};
+
+// Call from every thread of the work-group before the first lookup; the
+// caller's next __syncthreads() publishes the LDS copy.
+template <typename T>
+__device__ inline TauLookup<T> tau_lookup(const PlanView<T>& pv) {
+    if constexpr (std::is_same_v<T, float>) {
+        __shared__ float4 tl[kTauSeg];
+        for (int i = threadIdx.x; i < kTauSeg; i += blockDim.x) tl[i] = pv.tauseg[i];
+        return TauLookup<float>{tl};
+    } else {
+        return TauLookup<T>{pv.tau};
+    }
+}
 
 // Returns x unchanged but hides its value from the optimiser, so that
 // quantities derived from it inside a loop body are recomputed per iteration
@@ -465,9 +504,11 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             for (int i = 0; i < V; ++i) *at(a.out0, i, RO, j, lb) = v[i];
         }
     } else if constexpr (MODE == SMODE_XFILT) {
+        const TauLookup<T> taul = tau_lookup(pv);
         const uint32_t lb = lane_bytes(j);
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
+        __syncthreads();
         fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, c, j);
         // Eq. (1)-(2) on the spectrum held in registers (positions = axis-0 modes)
         const int s1 = signed_mode(o, N);
@@ -480,7 +521,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             const int s0 = signed_mode(k0, N);
             const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
             const bool zero = line_zero || (k0 == N / 2);
-            const T tau = pv.tau[zero ? 0 : n2] * (T)pv.amp_scale;  // tau[0] = 0: mean and Nyquist vanish
+            const T tau = taul(zero ? 0 : n2) * (T)pv.amp_scale;  // tau(0) = 0: mean and Nyquist vanish
             g[i] = mul_i(cscale(v[i], tau));
             v[i] = cscale(g[i], (T)s0);
         }
@@ -503,6 +544,8 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             }
         }
     } else if constexpr (MODE == SMODE_XADJ) {
+        const TauLookup<T> taul = tau_lookup(pv);
+        __syncthreads();
         const int s1 = signed_mode(o, N);
         const int s2 = col;
         const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
@@ -533,7 +576,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
                 const int s0 = signed_mode(k0, N);
                 const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
                 const bool zero = line_zero || (k0 == N / 2);
-                const T tau = pv.tau[zero ? 0 : n2] * (T)pv.amp_scale;
+                const T tau = taul(zero ? 0 : n2) * (T)pv.amp_scale;
                 v[i] = mul_i(cscale(acc[i], -tau));
             }
             fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);

@@ -51,8 +51,10 @@ struct Ops {
                                     cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)
     static int max_chunks(int n);
-    static hipError_t tau_table(T* tau, int64_t ntau, int n, double box, double amp_growth2, double gamma,
-                                double n_s, hipStream_t s);
+    // exact table tau[ntau]; for float plans also the piecewise-cubic
+    // segments (kTauSeg float4) the fused passes evaluate
+    static hipError_t tau_table(T* tau, int64_t ntau, float4* tauseg, int n, double box, double amp_growth2,
+                                double gamma, double n_s, hipStream_t s);
     // bytes of the fused path's workspace (three half spectra without the
     // k2 = N/2 plane) and of the inverse transform's scratch (one full half
     // spectrum)

@@ -300,10 +300,15 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
 }
 
 template <typename T>
-hipError_t Ops<T>::tau_table(T* tau, int64_t ntau, int n, double box, double amp_growth2, double gamma, double n_s,
-                             hipStream_t s) {
+hipError_t Ops<T>::tau_table(T* tau, int64_t ntau, float4* tauseg, int n, double box, double amp_growth2,
+                             double gamma, double n_s, hipStream_t s) {
     k_tau<T><<<capped_grid((uint64_t)ntau, 256), 256, 0, s>>>(tau, ntau, n, box, amp_growth2, gamma, n_s);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && tauseg) {
+        k_tauseg<T><<<(kTauSeg + 255) / 256, 256, 0, s>>>(tauseg, n, box, amp_growth2, gamma, n_s);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace gg
