@@ -12,7 +12,7 @@ in the order written below (no fused multiply-add).
 Box-Muller (G. E. P. Box and M. E. Muller, Ann. Math. Stat. 29 (1958) 610):
 from two uniforms u1 in (0, 1] and u2 in [0, 1),
     r = sqrt(-2 ln u1),  theta = 2 pi u2,  g_a = r cos theta,  g_b = r sin theta
-are two independent N(0,1) deviates.
+are two independent N(0,1) deviates; the noise field keeps g_a only.
 
 Uniforms from two 32-bit words (w_a, w_b):
     u1 = (w_a + 1) * 2^-32  (exact; never 0, so ln is finite)
@@ -117,7 +117,8 @@ def cos_sin_turn(w):
 
 
 def box_muller(wa, wb):
-    """Two N(0,1) deviates (g_a, g_b) from two 32-bit words each."""
+    """The Box-Muller pair (g_a, g_b) = r (cos theta, sin theta) from two
+    32-bit words each."""
     wa = np.asarray(wa, dtype=np.uint64)
     u1 = (wa + np.uint64(1)).astype(np.float64) * TWO_M32
     r = np.sqrt(-2.0 * log_unit(u1))
@@ -125,100 +126,6 @@ def box_muller(wa, wb):
     return r * cos_t, r * sin_t
 
 
-# ---------------------------------------------------------------------------
-# Binary32 variant, used by the single-precision path (whose arithmetic is
-# float32 throughout).  Same structure, every operation rounded once to
-# float32, series shortened to float32 accuracy (first omitted term below
-# 2^-27): atanh 5 coefficients, cos 6, sin 5.
-#
-# ln u1 from the word w_a, n = w_a + 1, u1 = n 2^-32:
-#   w_a >= 0xB504F333 (u1 > sqrt(1/2)): e = 0 and t = (u1-1)/(u1+1) is formed
-#     from the exact integer d = 2^32 - n as t = -RN(d) / RN(2^33 - d), so that
-#     ln u1 ~ -d 2^-32 keeps float32 relative accuracy as u1 -> 1;
-#   otherwise: u1 = RN(n) 2^-32 (one rounding), frexp, m in [sqrt(1/2),
-#     sqrt(2)), t = (m-1)/(m+1).
-# In both cases |t| <= 0.1716.  RN(.) of an integer is one rounding to float32.
-# The reduced angle uses RN of the (at most 30-bit) integer n.
-#
-# Pins: agreement with the binary64 deviates of the same words to a few
-# float32 ulp of max(1, |g|), and the float32 elementary functions against
-# extended-precision libm.
-# ---------------------------------------------------------------------------
-F32 = np.float32
-LN2_F32 = F32(0.6931471805599453)
-TWO_PI_F32 = F32(6.283185307179586)
-SQRT_HALF_F32 = F32(0.7071067811865476)
-TWO_M32_F32 = F32(2.0 ** -32)
-W_SPLIT = 0xB504F333  # smallest w_a with (w_a + 1) 2^-32 > sqrt(1/2)
-N_ATANH_F32 = 4
-N_COS_F32 = 5
-N_SIN_F32 = 4
-
-
-def _f32_coeffs():
-    at = [F32(1.0) / F32(2 * k + 1) for k in range(N_ATANH_F32 + 1)]
-    cc = [F32(-1.0 if k % 2 else 1.0) / F32(_factorial(2 * k)) for k in range(N_COS_F32 + 1)]
-    sc = [F32(-1.0 if k % 2 else 1.0) / F32(_factorial(2 * k + 1)) for k in range(N_SIN_F32 + 1)]
-    return at, cc, sc
-
-
-def _rn32(int_array):
-    """Round non-negative integers (< 2^53) once to float32."""
-    return np.asarray(int_array).astype(np.float64).astype(F32)
-
-
-def log_word_f32(wa):
-    """ln((w_a + 1) 2^-32) for 32-bit words w_a, float32 operation sequence."""
-    wa = np.asarray(wa, dtype=np.uint64)
-    near_one = wa >= np.uint64(W_SPLIT)
-    one = F32(1.0)
-    # u1 > sqrt(1/2): t from the exact complement d
-    d = np.uint64(0xFFFFFFFF) - wa
-    t_hi = -_rn32(d) / _rn32(np.uint64(1 << 33) - d)
-    # u1 <= sqrt(1/2): frexp of the rounded uniform
-    u = _rn32(wa + np.uint64(1)) * TWO_M32_F32
-    f, e = np.frexp(u)
-    f = f.astype(F32)
-    low = f < SQRT_HALF_F32
-    m = np.where(low, f * F32(2.0), f).astype(F32)
-    e = np.where(low, e - 1, e)
-    t_lo = (m - one) / (m + one)
-    t = np.where(near_one, t_hi, t_lo).astype(F32)
-    ef = np.where(near_one, 0, e).astype(F32)
-    s = t * t
-    at, _, _ = _f32_coeffs()
-    p = np.full_like(s, at[N_ATANH_F32])
-    for k in range(N_ATANH_F32 - 1, -1, -1):
-        p = p * s + at[k]
-    return ef * LN2_F32 + F32(2.0) * (t * p)
-
-
-def cos_sin_turn_f32(w):
-    """(cos, sin) of 2 pi w 2^-32 for 32-bit words w, float32 sequence."""
-    w = np.asarray(w, dtype=np.uint64)
-    q = (w >> np.uint64(30)).astype(np.int64)
-    rho = (w & np.uint64((1 << 30) - 1)).astype(np.int64)
-    direct = rho < (1 << 29)
-    n = _rn32(np.where(direct, rho, (1 << 30) - rho))
-    x = (n * TWO_M32_F32) * TWO_PI_F32
-    z = x * x
-    _, cc, sc = _f32_coeffs()
-    pc = np.full_like(z, cc[N_COS_F32])
-    for k in range(N_COS_F32 - 1, -1, -1):
-        pc = pc * z + cc[k]
-    ps = np.full_like(z, sc[N_SIN_F32])
-    for k in range(N_SIN_F32 - 1, -1, -1):
-        ps = ps * z + sc[k]
-    c, s = pc, x * ps
-    ca = np.where(direct, c, s)
-    sa = np.where(direct, s, c)
-    cos_t = np.select([q == 0, q == 1, q == 2], [ca, -sa, -ca], sa).astype(F32)
-    sin_t = np.select([q == 0, q == 1, q == 2], [sa, ca, -sa], -ca).astype(F32)
-    return cos_t, sin_t
-
-
-def box_muller_f32(wa, wb):
-    """Two float32 N(0,1) deviates from two 32-bit words each."""
-    r = np.sqrt(F32(-2.0) * log_word_f32(wa))
-    cos_t, sin_t = cos_sin_turn_f32(wb)
-    return r * cos_t, r * sin_t
+def gaussian(wa, wb):
+    """One N(0,1) deviate per word pair: the cosine branch r cos(2 pi u2)."""
+    return box_muller(wa, wb)[0]
