@@ -28,11 +28,11 @@
  *   The filter zeroes k = 0 and every mode with |s_j| = N/2 on any axis.
  * - Particle arrays: float32, structure of arrays, component j of cell c at
  *   j N^3 + c (3 N^3 values each for positions and velocities).
- * - Noise: cell c belongs to Philox-4x32-10 group g = c/4 (key = seed,
- *   counter = (g, stream_id, 0)); its four words give two Box-Muller pairs
- *   evaluated with a fixed operation sequence (binary64 on the double path,
- *   binary32 on the float path), so a cell's value depends only on
- *   (seed, stream_id, c).  The two precisions agree to a few float ulp.
+ * - Noise: cell c is one Philox-4x32-10 call (key = seed, counter =
+ *   (c, stream_id, 0)); its words w0, w1 give the cosine branch of the
+ *   Box-Muller transform, sqrt(-2 ln u1) cos(2 pi u2), evaluated in binary64
+ *   with a fixed operation sequence, so a cell's value depends only on
+ *   (seed, stream_id, c).  The float path stores that value rounded once.
  *
  * Memory, streams, errors
  * -----------------------

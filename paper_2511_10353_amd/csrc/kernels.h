@@ -94,20 +94,13 @@ __device__ __forceinline__ int opaque(int x) {
 __device__ __forceinline__ int signed_mode(int k, int n) { return k < (n >> 1) ? k : k - n; }
 
 // ---------------------------------------------------------------------------
-// White noise, four cells per thread.
+// White noise, one cell per thread and iteration.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_noise(T* __restrict__ w, uint64_t ngroups, uint64_t seed, uint32_t stream) {
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        T d[4];
-        noise_group<T>(g, seed, stream, d);
-        T* o = w + 4 * g;
-        o[0] = d[0];
-        o[1] = d[1];
-        o[2] = d[2];
-        o[3] = d[3];
-    }
+__global__ void k_noise(T* __restrict__ w, uint64_t ncells, uint64_t seed, uint32_t stream) {
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
+         c += (uint64_t)gridDim.x * blockDim.x)
+        w[c] = noise_value<T>(c, seed, stream);
 }
 
 // Lattice coordinates (m0, m1) of spectrum row r.  Plain rows are r = m0 N + m1;
@@ -189,15 +182,14 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
     const uint64_t line0 = row0 + (uint64_t)blockIdx.x * L;
 
     if constexpr (SRC == ZSRC_NOISE) {
-        // group q of a line covers cells 4q..4q+3 = complex slots 2q, 2q+1
-        for (int gi = t; gi < L * (N / 4); gi += NT) {
-            const int cc = gi % L, q = gi / L;
+        // complex slot p of a line holds cells 2p, 2p+1; sixteen lanes fill one
+        // slot row of the tile (sixteen lines)
+        for (int si = t; si < L * M; si += NT) {
+            const int cc = si % L, p = si / L;
             int m0, m1;
             row_coords<BLK>(line0 + cc, N, m0, m1);
-            T d[4];
-            noise_group<T>(((uint64_t)m0 * N + m1) * (N / 4) + q, seed, stream, d);
-            lds[lidx<L>(2 * q, cc)] = {d[0], d[1]};
-            lds[lidx<L>(2 * q + 1, cc)] = {d[2], d[3]};
+            const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * p;
+            lds[lidx<L>(p, cc)] = {noise_value<T>(cell, seed, stream), noise_value<T>(cell + 1, seed, stream)};
         }
     } else {
         // four consecutive reals (two packed complex slots) per lane

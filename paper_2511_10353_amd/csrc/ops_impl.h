@@ -36,6 +36,20 @@ struct ZLines {
                                  : Tile<T>::L;
 };
 
+// Lines per work-group of the first pass (noise + axis-2 transform): its LDS
+// tile is kept to GG_P1_LDS bytes so that a work-group of it fits on a compute
+// unit beside one of the axis-1 pass (128 KB of LDS at N = 1024), letting the
+// pipelined chunks of the two passes share compute units (noise arithmetic
+// alongside memory-bound transposes).
+#ifndef GG_P1_LDS
+#define GG_P1_LDS 32768
+#endif
+template <typename T, int N>
+struct P1Lines {
+    static constexpr int fit = GG_P1_LDS / (int)((N / 2) * sizeof(cx<T>));
+    static constexpr int L = fit >= ZLines<T, N>::L ? ZLines<T, N>::L : (fit >= 1 ? fit : 1);
+};
+
 inline unsigned capped_grid(uint64_t work, unsigned block) {
     uint64_t g = (work + block - 1) / block;
     const uint64_t cap = 256ull * 64ull;
@@ -75,8 +89,7 @@ hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipSt
 template <typename T>
 hipError_t Ops<T>::noise(const PlanView<T>& pv, uint64_t seed, uint32_t stream_id, T* w, hipStream_t s) {
     const uint64_t n3 = (uint64_t)pv.n * pv.n * pv.n;
-    const uint64_t groups = n3 / 4;
-    k_noise<T><<<capped_grid(groups, 256), 256, 0, s>>>(w, groups, seed, stream_id);
+    k_noise<T><<<capped_grid(n3, 256), 256, 0, s>>>(w, n3, seed, stream_id);
     return hipGetLastError();
 }
 
@@ -195,15 +208,16 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
         for (int s = 0; s < NC; ++s) {
             launch = s;
             const uint64_t row0 = (uint64_t)s * xh * 8 * N;
-            const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / LZ);
+            constexpr int L1 = P1Lines<T, N>::L;
+            const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / L1);
             GG_TRY(mark(sa, 0))
             if (w) {
                 const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
-                k_zfwd<T, N, ZSRC_REAL, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0, 0u,
+                k_zfwd<T, N, ZSRC_REAL, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0, 0u,
                                                                                                   row0);
             } else {
                 const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
-                k_zfwd<T, N, ZSRC_NOISE, false, true, LZ><<<blocks, LZ * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, seed,
+                k_zfwd<T, N, ZSRC_NOISE, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, seed,
                                                                                                    0u, row0);
             }
             GG_TRY(hipGetLastError())

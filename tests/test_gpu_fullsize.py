@@ -26,6 +26,25 @@ def _rel_rms_t(a, b):
     return float(torch.sqrt(d / b.double().pow(2).sum()))
 
 
+def test_float_noise_is_rounded_double_noise_at_1024():
+    # the float path's noise is the binary64 deviate rounded once, for every
+    # one of the 2^30 cells (its fast evaluation falls back to the defining
+    # sequence near rounding boundaries; a wrong error bound would show here)
+    say("[1024] noise f32 vs rounded f64, all cells")
+    p64 = gg.Plan(N, BOX, gg.Cosmo(), dtype="f64")
+    p32 = gg.Plan(N, BOX, gg.Cosmo(), dtype="f32")
+    for seed, stream in ((SEED, 0), (7, 3)):
+        w64 = p64.noise(seed, stream_id=stream)
+        w32 = p32.noise(seed, stream_id=stream)
+        bad = int((w64.float() != w32).sum())
+        say(f"[1024] seed {seed} stream {stream}: {bad} mismatching cells")
+        assert bad == 0
+        del w64, w32
+    p64.close()
+    p32.close()
+    torch.cuda.empty_cache()
+
+
 def test_fp32_matches_fp64_at_1024():
     say(f"[1024] FP64 make_ic")
     p64 = gg.Plan(N, BOX, gg.Cosmo(), dtype="f64")
