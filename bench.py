@@ -48,8 +48,8 @@ def stored_traffic(pass_name):
         return None
     for line in text.splitlines():
         cols = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cols) == 7 and cols[0] == pass_name:
-            return float(cols[4]) * 1e9
+        if len(cols) == 8 and cols[0] == pass_name:
+            return float(cols[5]) * 1e9
     return None
 
 
