@@ -186,6 +186,30 @@ gg_status gg_make_ic_adjoint(const gg_plan* plan, const void* g_psi, const float
                              double amp_scale, const void* psi, double* g_log_amp, void* g_w, void* work,
                              void* stream);
 
+/* The density field of Eq. (1) alone: delta = inverse transform of
+ * sqrt(P N^3/L^3) W~ (mean and Nyquist planes zero), one R array in the
+ * plan's dtype.  W is the noise of `seed` (stream_id 0) or, if w_opt is not
+ * NULL, the R field w_opt.  work: gg_workspace_bytes(plan); delta must not
+ * overlap work or w_opt.  Five passes on `stream`. */
+gg_status gg_make_density(const gg_plan* plan, uint64_t seed, const void* w_opt, void* delta, void* work,
+                          void* stream);
+
+/* Binned power spectrum of a real field (R, plan dtype; Sec. 2.1 lists the
+ * density power spectrum among the outputs).  Every mode n != 0 of the field's
+ * transform F with b = floor(|n|) < nbins (|n| in units of k_f = 2 pi / L)
+ * falls in bin b; pk[b] = (L^3/N^6) <|F|^2>, kmean[b] = k_f <|n|>, counts[b]
+ * = number of modes (both halves of the spectrum), all as device doubles
+ * (nbins each, 8-byte aligned).  1 <= nbins <= 1024.  work holds the
+ * transform and per-work-group partial sums (gg_workspace_bytes(plan)).
+ * Sums are binary64 in a fixed order (deterministic). */
+gg_status gg_power_spectrum(const gg_plan* plan, const void* field, int32_t nbins, double* pk, double* kmean,
+                            double* counts, void* work, void* stream);
+
+/* out[0..3] (device doubles) = mean, standard deviation (population),
+ * minimum and maximum of the N^3 values of field (R, plan dtype), in a fixed
+ * summation order.  work: gg_workspace_bytes(plan) (partial sums). */
+gg_status gg_field_stats(const gg_plan* plan, const void* field, double* out, void* work, void* stream);
+
 /* Per-pass timing of gg_make_ic with HIP events recorded on the call's
  * stream.  Enable before the calls to time; gg_timing_read waits for the last
  * recorded call and returns, for each of the npass passes, the summed

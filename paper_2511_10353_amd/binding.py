@@ -75,6 +75,9 @@ _SIGS = {
     "gg_make_ic": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP]),
     "gg_make_ic_from_noise": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
     "gg_make_ic_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
+    "gg_make_density": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP]),
+    "gg_power_spectrum": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "gg_field_stats": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -250,6 +253,35 @@ class Plan:
         _check(lib().gg_make_ic_adjoint(self._h, _ptr(g_psi), _ptr(g_pos), _ptr(g_vel), float(amp_scale), _ptr(psi),
                                         _ptr(g_la), _ptr(g_w), _ptr(work), _stream()))
         return (g_w, g_la) if want_log_amp else g_w
+
+    def make_density(self, seed=42, w=None, out=None, work=None):
+        """delta (Eq. 1) from the noise of ``seed`` or from the field ``w``."""
+        if w is not None:
+            w = self._need(w, self._real_shape(), self.real_dtype, "w")
+        out = self._need(out, self._real_shape(), self.real_dtype, "out")
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_make_density(self._h, int(seed), _ptr(w), _ptr(out), _ptr(work), _stream()))
+        return out
+
+    def power_spectrum(self, field, nbins, work=None):
+        """(pk, kmean, counts): float64 device tensors of length nbins."""
+        field = self._need(field, self._real_shape(), self.real_dtype, "field")
+        res = torch.empty((3, int(nbins)), dtype=torch.float64, device="cuda")
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_power_spectrum(self._h, _ptr(field), int(nbins), _ptr(res[0]), _ptr(res[1]), _ptr(res[2]),
+                                       _ptr(work), _stream()))
+        return res[0], res[1], res[2]
+
+    def field_stats(self, field, work=None):
+        """float64 device tensor (mean, std, min, max) of the N^3 values."""
+        field = self._need(field, self._real_shape(), self.real_dtype, "field")
+        out = torch.empty(4, dtype=torch.float64, device="cuda")
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_field_stats(self._h, _ptr(field), _ptr(out), _ptr(work), _stream()))
+        return out
 
     def timing_enable(self, on=True):
         _check(lib().gg_timing_enable(self._h, 1 if on else 0))

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "gg.h"
+#include "diag.h"
 #include "kernels.h"
 #include "ops.h"
 
@@ -508,6 +509,77 @@ gg_status gg_make_ic_adjoint(const gg_plan* pc, const void* g_psi, const float* 
                                     g_log_amp, static_cast<float*>(g_w), static_cast<gg::cx<float>*>(work), s);
     }
     return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic_adjoint launch");
+}
+
+gg_status gg_make_density(const gg_plan* pc, uint64_t seed, const void* w_opt, void* delta, void* work,
+                          void* stream) {
+    if (!pc || !delta || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_make_density");
+    if (!aligned(delta) || !aligned(work) || (w_opt && !aligned(w_opt)))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t rb = (size_t)pc->n * pc->n * pc->n * elem_size(pc->dtype);
+    const size_t wb = gg_workspace_bytes(pc);
+    if (overlap(delta, rb, work, wb) || (w_opt && (overlap(w_opt, rb, work, wb) || overlap(w_opt, rb, delta, rb))))
+        return fail(GG_ERR_INVALID_ARG, "delta, w_opt and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e =
+        pc->dtype == GG_F64
+            ? gg::Ops<double>::density(view<double>(pc), seed, static_cast<const double*>(w_opt),
+                                       static_cast<double*>(delta), static_cast<gg::cx<double>*>(work), s)
+            : gg::Ops<float>::density(view<float>(pc), seed, static_cast<const float*>(w_opt), static_cast<float*>(delta),
+                                      static_cast<gg::cx<float>*>(work), s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "make_density launch");
+}
+
+gg_status gg_power_spectrum(const gg_plan* pc, const void* field, int32_t nbins, double* pk, double* kmean,
+                            double* counts, void* work, void* stream) {
+    if (!pc || !field || !pk || !kmean || !counts || !work)
+        return fail(GG_ERR_INVALID_ARG, "null argument to gg_power_spectrum");
+    if (nbins < 1 || nbins > gg::kPkMaxBins) return fail(GG_ERR_INVALID_ARG, "nbins must be in [1, 1024]");
+    if (!aligned(field) || !aligned(work) || ((uintptr_t)pk & 7u) || ((uintptr_t)kmean & 7u) || ((uintptr_t)counts & 7u))
+        return fail(GG_ERR_INVALID_ARG, "field and work must be 256-byte aligned, outputs 8-byte aligned");
+    const size_t rb = (size_t)pc->n * pc->n * pc->n * elem_size(pc->dtype);
+    const size_t wb = gg_workspace_bytes(pc);
+    const size_t ob = (size_t)nbins * sizeof(double);
+    if (overlap(field, rb, work, wb) || overlap(pk, ob, work, wb) || overlap(kmean, ob, work, wb) ||
+        overlap(counts, ob, work, wb) || overlap(pk, ob, kmean, ob) || overlap(pk, ob, counts, ob) ||
+        overlap(kmean, ob, counts, ob))
+        return fail(GG_ERR_INVALID_ARG, "field, outputs and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e =
+        pc->dtype == GG_F64
+            ? gg::Ops<double>::power_spectrum(view<double>(pc), static_cast<const double*>(field), nbins, pk, kmean,
+                                              counts, static_cast<gg::cx<double>*>(work), wb, s)
+            : gg::Ops<float>::power_spectrum(view<float>(pc), static_cast<const float*>(field), nbins, pk, kmean, counts,
+                                             static_cast<gg::cx<float>*>(work), wb, s);
+    if (e == hipErrorInvalidValue) return fail(GG_ERR_INVALID_ARG, "workspace too small for the requested bins");
+    return e == hipSuccess ? GG_OK : fail_hip(e, "power_spectrum launch");
+}
+
+gg_status gg_field_stats(const gg_plan* pc, const void* field, double* out, void* work, void* stream) {
+    if (!pc || !field || !out || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_field_stats");
+    if (!aligned(field) || !aligned(work) || ((uintptr_t)out & 7u))
+        return fail(GG_ERR_INVALID_ARG, "field and work must be 256-byte aligned, out 8-byte aligned");
+    const uint64_t count = (uint64_t)pc->n * pc->n * pc->n;
+    const size_t rb = count * elem_size(pc->dtype);
+    const size_t wb = gg_workspace_bytes(pc);
+    if (overlap(field, rb, work, wb) || overlap(out, 4 * sizeof(double), work, wb) ||
+        overlap(out, 4 * sizeof(double), field, rb))
+        return fail(GG_ERR_INVALID_ARG, "field, out and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    const size_t fit = wb / (3 * sizeof(double));
+    const int nblocks = (int)(fit < 1024 ? fit : 1024);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* scratch = static_cast<double*>(work);
+    const hipError_t e =
+        pc->dtype == GG_F64
+            ? gg::Ops<double>::field_stats(static_cast<const double*>(field), count, out, scratch, nblocks, s)
+            : gg::Ops<float>::field_stats(static_cast<const float*>(field), count, out, scratch, nblocks, s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "field_stats launch");
 }
 
 gg_status gg_timing_enable(gg_plan* p, int on) {

@@ -413,11 +413,13 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
 //   SMODE_XADJ (A3)       : adjoint of P3 + P4's axis-0 work: forward transforms of
 //                           in0, in1, in2 (component spectra of the gradient),
 //                           S = -i tau (s0 X0 + s1 X1 + s2 X2), inverse -> out0
+//   SMODE_XDELTA          : axis 0, o = k1: forward of in0, Eq. (1) factor
+//                           sqrt(P N^3 / L^3) / N^3 = tau n^2 k_f, inverse -> out0
 // A thread keeps one line's registers only: where a second transform of the
 // same input is needed, the tile is read again (the re-read is served by the
 // caches) rather than held, which keeps the kernels free of register spills.
 // ---------------------------------------------------------------------------
-enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3, SMODE_XADJ = 4 };
+enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3, SMODE_XADJ = 4, SMODE_XDELTA = 5 };
 
 template <typename T>
 struct StridedArgs {
@@ -577,6 +579,33 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb) = v[i];
             }
+        }
+    } else if constexpr (MODE == SMODE_XDELTA) {
+        const TauLookup<T> taul = tau_lookup(pv);
+        const uint32_t lb = lane_bytes(j);
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
+        __syncthreads();
+        fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, c, j);
+        const int s1 = signed_mode(o, N);
+        const int s2 = col;
+        const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
+        const T kf = (T)(2.0 * 3.14159265358979323846 / pv.box);
+        const int jj = opaque(j), cc = opaque(c);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const int k0 = last_pos<N, -1>(jj, i);
+            const int s0 = signed_mode(k0, N);
+            const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
+            const bool zero = line_zero || (k0 == N / 2);
+            const T f = taul(zero ? 0 : n2) * ((T)n2 * kf);
+            v[i] = cscale(v[i], f);
+        }
+        fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+        const uint32_t lb2 = lane_bytes(jj);
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb2) = v[i];
         }
     } else {  // SMODE_YINV3
         {

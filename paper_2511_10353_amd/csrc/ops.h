@@ -47,6 +47,17 @@ struct Ops {
     // optionally d loss/d log A = (1/2) sum g psi (one FP64 value at g_log_amp)
     static hipError_t adjoint(const PlanView<T>& pv, const T* gpsi, const float* gpos, const float* gvel,
                               const T* psi, double* g_log_amp, T* gw, cx<T>* work, hipStream_t s);
+    // Eq. (1) alone: the density field delta (plain real layout) from the noise
+    // of seed, or from w if not null
+    static hipError_t density(const PlanView<T>& pv, uint64_t seed, const T* w, T* delta, cx<T>* work,
+                              hipStream_t s);
+    // binned power spectrum of a real field (pk, kmean, counts: nbins doubles);
+    // the transform and the partial sums live in work
+    static hipError_t power_spectrum(const PlanView<T>& pv, const T* field, int nbins, double* pk, double* kmean,
+                                     double* counts, cx<T>* work, size_t work_bytes, hipStream_t s);
+    // out[0..3] = mean, standard deviation, min, max of count values
+    static hipError_t field_stats(const T* field, uint64_t count, double* out, double* scratch, int nblocks,
+                                  hipStream_t s);
     static hipError_t fused_forward(const PlanView<T>& pv, const T* w, uint64_t seed, float* pos, float* vel, T* psi,
                                     cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)

@@ -3,6 +3,7 @@
 #include <type_traits>
 
 #include "cosmo_dev.h"
+#include "diag.h"
 #include "kernels.h"
 #include "ops.h"
 
@@ -311,6 +312,80 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
 #undef GG_TRY
         return hipSuccess;
     });
+}
+
+template <typename T>
+hipError_t Ops<T>::density(const PlanView<T>& pv, uint64_t seed, const T* w, T* delta, cx<T>* work, hipStream_t s) {
+    return dispatch_n(pv.n, [&](auto nc) -> hipError_t {
+        constexpr int N = decltype(nc)::value;
+        constexpr int M = N / 2;
+        constexpr int LZ = ZLines<T, N>::L;
+        constexpr int L1 = P1Lines<T, N>::L;
+        cx<T>* b0 = work;
+        hipError_t e;
+#define GG_TRY(expr) \
+    if ((e = (expr)) != hipSuccess) return e;
+        const int64_t H = (int64_t)8 * N * M;
+        const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+        if (w)
+            k_zfwd<T, N, ZSRC_REAL, false, true, L1><<<N * N / L1, L1 * PlanInfo<M>::TPL, 0, s>>>(zs, b0, pv.tw, 0, 0u, 0);
+        else
+            k_zfwd<T, N, ZSRC_NOISE, false, true, L1><<<N * N / L1, L1 * PlanInfo<M>::TPL, 0, s>>>(zs, b0, pv.tw, seed,
+                                                                                                 0u, 0);
+        GG_TRY(hipGetLastError())
+        GG_TRY((launch_strided<T, N, SMODE_FWD>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
+                                                pv, s)))
+        GG_TRY((launch_strided<T, N, SMODE_XDELTA, true>(
+            strided_args<T>(b0, nullptr, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M), pv, s)))
+        GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
+                                                pv, s)))
+        k_zinv<T, N, 0, true, LZ><<<dim3(N * N / LZ, 1), LZ * PlanInfo<M>::TPL, 0, s>>>(b0, b0, b0, M, delta, (T)1, pv,
+                                                                                        ZelArgs{nullptr, nullptr, nullptr});
+        GG_TRY(hipGetLastError())
+#undef GG_TRY
+        return hipSuccess;
+    });
+}
+
+template <typename T>
+hipError_t Ops<T>::power_spectrum(const PlanView<T>& pv, const T* field, int nbins, double* pk, double* kmean,
+                                  double* counts, cx<T>* work, size_t work_bytes, hipStream_t s) {
+    const int n = pv.n;
+    const size_t spec_bytes = (size_t)n * n * (n / 2 + 1) * sizeof(cx<T>);
+    const size_t part_off = (spec_bytes + 255) / 256 * 256;
+    if (nbins < 1 || nbins > kPkMaxBins || part_off >= work_bytes) return hipErrorInvalidValue;
+    // work-groups: a power of two dividing the N^2 rows, at most 1024, whose
+    // partial sums fit behind the spectrum
+    const size_t per_block = (size_t)3 * nbins * sizeof(double);
+    int64_t nblocks = 1;
+    while (nblocks * 2 <= 1024 && nblocks * 2 <= (int64_t)n * n && (size_t)(nblocks * 2) * per_block <= work_bytes - part_off)
+        nblocks *= 2;
+    if ((size_t)nblocks * per_block > work_bytes - part_off) return hipErrorInvalidValue;
+    hipError_t e = fft_forward(pv, field, work, s);
+    if (e != hipSuccess) return e;
+    double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + part_off);
+    const size_t shmem = (size_t)3 * nbins * sizeof(double) + 3 * kPkThreads * sizeof(double) + kPkThreads * sizeof(int);
+    k_pk_rows<T><<<(unsigned)nblocks, kPkThreads, shmem, s>>>(work, n, nbins, (int)((int64_t)n * n / nblocks), part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const double n3 = (double)n * n * n;
+    k_pk_final<T><<<(nbins + 255) / 256, 256, 0, s>>>(part, (int)nblocks, nbins, pv.box * pv.box * pv.box / (n3 * n3),
+                                                      2.0 * 3.14159265358979323846 / pv.box, pk, kmean, counts);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Ops<T>::field_stats(const T* field, uint64_t count, double* out, double* scratch, int nblocks,
+                               hipStream_t s) {
+    if (nblocks < 1 || count == 0) return hipErrorInvalidValue;
+    k_stats_partial<T, false><<<nblocks, kStatThreads, 0, s>>>(field, count, nullptr, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_stats_final<T, false><<<1, 1, 0, s>>>(scratch, nblocks, count, out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_stats_partial<T, true><<<nblocks, kStatThreads, 0, s>>>(field, count, out, scratch);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_stats_final<T, true><<<1, 1, 0, s>>>(scratch, nblocks, count, out);
+    return hipGetLastError();
 }
 
 template <typename T>
