@@ -1,0 +1,179 @@
+"""Pins for the oracle's white-noise refinement (App. A) and the Eq. 4-5
+combination of two resolutions."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cosmology, noise, pipeline, refine
+from tests import inputs
+
+COSMO = cosmology.Cosmology()
+
+
+@pytest.mark.parametrize("variant", ["hr", "3", "4", "linear", "sine"])
+def test_bases_are_orthonormal(variant):
+    e = refine.E_BASIS[variant]
+    assert np.abs(e @ e.T - np.eye(e.shape[0])).max() < 1e-15
+    nl, _ = refine.patch_sizes(variant)
+    f = refine.F_BASIS[nl]
+    assert np.abs(f @ f.T - np.eye(nl)).max() < 1e-15
+
+
+@pytest.mark.parametrize("variant", ["4", "linear", "sine"])
+def test_low_basis_functions_match_parent_symmetry(variant):
+    # E_0 constant, E_1 odd about the patch centre (no systematic shift)
+    e = refine.E_BASIS[variant]
+    assert np.allclose(e[0], e[0][0]) and np.allclose(e[1], -e[1][::-1])
+
+
+def _patch_1d(v0, v1, rands, variant):
+    """1D refinement of two parent cells through the 3D code: a patch whose
+    values do not vary along axes 1 and 2 is the 1D patch times F_0 F_0."""
+    nl, nh = refine.patch_sizes(variant)
+    v = np.zeros((nl, nl, nl))
+    f0 = refine.F_BASIS[nl][0]
+    for m, val in enumerate([v0, v1][:nl]):
+        v[m] = val * np.outer(f0, f0)  # coefficient a_i00 = 1D coefficient a_i
+    new = np.zeros((nh, nh, nh))
+    for j, r in enumerate(rands):
+        new[nl + j, 0, 0] = r
+    child = refine.expand_patches(v, new, variant)
+    e0 = refine.E_BASIS[variant][0]
+    return child[:, 0, 0] / (e0[0] * e0[0])
+
+
+def test_hoffman_ribak_step():
+    # Eq. A.4
+    v, r = 0.7, -1.3
+    got = _patch_1d(v, None, [r], "hr")
+    assert np.allclose(got, [(v - r) / math.sqrt(2), (v + r) / math.sqrt(2)], rtol=0, atol=1e-15)
+
+
+def test_three_cell_patch_formula():
+    # Eq. A.15
+    v0, v1, r = 0.31, -1.12, 0.57
+    s6 = math.sqrt(6)
+    want = [(v0 + v1 - r) / s6 - (v1 - v0) / 2, (v0 + v1 + 2 * r) / s6, (v0 + v1 - r) / s6 + (v1 - v0) / 2]
+    assert np.allclose(_patch_1d(v0, v1, [r], "3"), want, rtol=0, atol=1e-15)
+
+
+def test_four_cell_patch_formula():
+    # Eq. A.16-A.19
+    v0, v1, r1, r2 = -0.44, 1.9, 0.83, -0.26
+    s7, s8, s2 = math.sqrt(7), math.sqrt(8), math.sqrt(2)
+    d = v1 - v0
+    want = [(v0 + v1) / s8 - s7 * d / (4 * s2) - r1 / 2 + r2 / 4,
+            (v0 + v1) / s8 - d / (4 * s2) + r1 / 2 - s7 * r2 / 4,
+            (v0 + v1) / s8 + d / (4 * s2) + r1 / 2 + s7 * r2 / 4,
+            (v0 + v1) / s8 + s7 * d / (4 * s2) - r1 / 2 - r2 / 4]
+    assert np.allclose(_patch_1d(v0, v1, [r1, r2], "4"), want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("variant", ["hr", "3", "4", "linear", "sine"])
+def test_tensor_product_and_parent_coefficients(variant):
+    nl, nh = refine.patch_sizes(variant)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((5, nl, nl, nl))
+    new = rng.standard_normal((5, nh, nh, nh))
+    child = refine.expand_patches(v, new, variant)
+    e = refine.E_BASIS[variant]
+    f = refine.F_BASIS[nl]
+    # projecting the child patch on E_i E_j E_k gives back every coefficient
+    a = np.einsum("pmnl,im,jn,kl->pijk", child, e, e, e)
+    low = np.einsum("pmnl,im,jn,kl->pijk", v, f, f, f)
+    assert np.abs(a[:, :nl, :nl, :nl] - low).max() < 1e-14
+    mask = np.ones((nh, nh, nh), bool)
+    mask[:nl, :nl, :nl] = False
+    assert np.abs(a[:, mask] - new[:, mask]).max() < 1e-14
+    # an explicit triple sum over the 3D basis functions (Eq. A.28)
+    full = new.copy()
+    full[:, :nl, :nl, :nl] = low
+    one = sum(full[0, i, j, k] * np.einsum("m,n,l->mnl", e[i], e[j], e[k])
+              for i in range(nh) for j in range(nh) for k in range(nh))
+    assert np.abs(one - child[0]).max() < 1e-14
+
+
+@pytest.mark.parametrize("variant", ["hr", "4", "3"])
+def test_refined_noise_is_white(variant):
+    nl, nh = refine.patch_sizes(variant)
+    parent = noise.noise_grid(32, 5)
+    child = refine.refine(parent, variant, seed=11, stream=1)
+    assert child.shape == (32 // nl * nh,) * 3
+    x = child.ravel()
+    m = x.size
+    assert abs(x.mean()) < 5 / math.sqrt(m)
+    assert abs(x.var() - 1) < 5 * math.sqrt(2 / m)
+    for lag in (1, 2, 3, nh, nh * 32 // nl):
+        assert abs(np.corrcoef(x[:-lag], x[lag:])[0, 1]) < 5 / math.sqrt(m)
+
+
+def test_refined_noise_uses_philox_coefficients():
+    parent = noise.noise_grid(4, 1)
+    child = refine.refine(parent, "4", seed=99, stream=7)
+    # patch (0, 0, 1): coefficient (2, 3, 0) is noise value (patch 1) * 64 + 2*16 + 3*4 + 0
+    e = refine.E_BASIS["4"]
+    blk = child[0:4, 0:4, 4:8]
+    a = np.einsum("mnl,im,jn,kl->ijk", blk, e, e, e)
+    assert abs(a[2, 3, 0] - noise.noise_cells([64 + 44], 99, 7)[0]) < 1e-14
+
+
+def test_cic_upsample_exact_cases():
+    n = 8
+    const = np.full((n, n, n), 1.75)
+    assert np.abs(refine.cic_upsample(const, 2) - 1.75).max() < 1e-15
+    ramp = np.tile(np.arange(n, dtype=np.float64).reshape(n, 1, 1), (1, n, n))
+    up = refine.cic_upsample(ramp, 2)
+    # linear inside the period (the last interval wraps from n-1 to 0)
+    assert np.abs(up[: 2 * n - 1, 3, 5] - np.arange(2 * n - 1) / 2).max() < 1e-15
+    assert abs(up[2 * n - 1, 0, 0] - (n - 1) / 2) < 1e-15
+    # even child points are the parent samples
+    f = inputs.real_field(n, 2)
+    assert np.abs(refine.cic_upsample(f, 2)[::2, ::2, ::2] - f).max() < 1e-15
+
+
+def test_windows_partition_the_modes():
+    n, box, r_s = 32, 100.0, 2 * 100.0 / 16
+    big = refine.mode_window(n, box, r_s, "large")
+    small = refine.mode_window(n, box, r_s, "small")
+    assert np.array_equal(big + small, np.ones_like(big))
+    # the cutoff: k r_s < 1 with r_s two parent cells, |n| < N_p / (4 pi)
+    s = pipeline.signed_index(n)
+    n2 = (s.reshape(n, 1, 1) ** 2 + s.reshape(1, n, 1) ** 2 + np.arange(n // 2 + 1).reshape(1, 1, -1) ** 2)
+    assert np.array_equal(big > 0, n2 < (16 / (4 * math.pi)) ** 2)
+
+
+def test_large_plus_small_is_the_full_field_on_one_grid():
+    n, box = 32, 150.0
+    w = noise.noise_grid(n, 8)
+    r_s = 2 * box / 16
+    full = np.stack(pipeline.displacement_fields(w, n, box, COSMO))
+    parts = (refine.windowed_displacements(w, n, box, COSMO, r_s, "small") +
+             refine.windowed_displacements(w, n, box, COSMO, r_s, "large"))
+    assert np.abs(parts - full).max() < 1e-14 * np.abs(full).max()
+
+
+def test_combine_without_large_scales_is_the_child_field():
+    n_p, n_c, box = 16, 32, 120.0
+    wp = noise.noise_grid(n_p, 1)
+    wc = noise.noise_grid(n_c, 2)
+    r_s = box  # k r_s >= 2 pi for every mode but k = 0: no large-scale part
+    psi = refine.combine(wp, wc, box, COSMO, r_s)
+    full = np.stack(pipeline.displacement_fields(wc, n_c, box, COSMO))
+    assert np.abs(psi - full).max() < 1e-14 * np.abs(full).max()
+
+
+def test_combine_keeps_parent_large_scales():
+    # child noise refined from the parent: the combined field's low modes follow
+    # the parent's (CiC plus deconvolution reproduces them to a few percent)
+    n_p, box = 32, 200.0
+    wp = noise.noise_grid(n_p, 4)
+    wc = refine.refine(wp, "4", seed=5, stream=1)
+    r_s = 2 * box / n_p
+    psi = refine.combine(wp, wc, box, COSMO, r_s)
+    large_p = refine.windowed_displacements(wp, n_p, box, COSMO, r_s, "large")
+    lowc = pipeline.forward(psi[0])[: 3, : 3, : 3] / (2 * n_p) ** 3
+    lowp = pipeline.forward(large_p[0])[: 3, : 3, : 3] / n_p ** 3
+    sel = np.abs(lowp) > 1e-6 * np.abs(lowp).max()  # modes with k_0 = 0 vanish in psi_0
+    rel = np.abs(lowc[sel] - lowp[sel]) / np.abs(lowp[sel])
+    assert sel.sum() >= 8 and rel.max() < 0.01
