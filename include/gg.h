@@ -210,6 +210,41 @@ gg_status gg_power_spectrum(const gg_plan* plan, const void* field, int32_t nbin
  * summation order.  work: gg_workspace_bytes(plan) (partial sums). */
 gg_status gg_field_stats(const gg_plan* plan, const void* field, double* out, void* work, void* stream);
 
+/* White-noise refinement (App. A): each patch of N_L^3 parent cells is
+ * replaced by N_H^3 child cells whose expansion on the tensor-product basis
+ * E_i E_j E_k keeps the parent's coefficients (on F_i F_j F_k) and takes
+ * every other coefficient from the noise (Philox value of index
+ * p N_H^3 + (i N_H + j) N_H + k for patch p, row-major over the patch grid,
+ * with seed and stream_id; binary64).  variant selects the 1D bases:
+ *   GG_REFINE_HR      N_L = 1, N_H = 2 (Eq. A.2-A.4)
+ *   GG_REFINE_3       N_L = 2, N_H = 3 (Eq. A.7-A.9; factor 3/2)
+ *   GG_REFINE_4       N_L = 2, N_H = 4 (Eq. A.10-A.13; the default basis)
+ *   GG_REFINE_LINEAR  N_L = 2, N_H = 4 (Eq. A.20-A.23)
+ *   GG_REFINE_SINE    N_L = 2, N_H = 4 (Eq. A.24-A.27)
+ * parent: n_parent^3 values of dtype; child: (n_parent / N_L * N_H)^3 values
+ * (device pointers, 256-byte aligned, not overlapping).  Runs on the current
+ * device; computed in binary64 and rounded once to dtype. */
+typedef enum { GG_REFINE_HR = 0, GG_REFINE_3 = 1, GG_REFINE_4 = 2, GG_REFINE_LINEAR = 3, GG_REFINE_SINE = 4 } gg_refine;
+gg_status gg_refine_noise(int32_t n_parent, gg_dtype dtype, gg_refine variant, const void* parent, uint64_t seed,
+                          uint32_t stream_id, void* child, void* stream);
+
+/* Displacements psi (3 R arrays, plan dtype) of the noise field w (R) with
+ * the filter restricted to a window of modes, for combining two resolutions
+ * (Eq. 4-5): modes with n^2 < n2_min or n^2 >= n2_max are dropped (n2_max
+ * <= 0: no upper bound), and, if cic_deconvolve is set, the kept modes are
+ * divided by the cloud-in-cell window prod_j sinc^2(pi s_j / N).  With a
+ * cutoff scale r_s, Eq. 5 (large scales, k r_s < 1) is n2_max =
+ * ceil((L / (2 pi r_s))^2) and Eq. 4 (small scales) n2_min = the same value.
+ * work: gg_workspace_bytes(plan). */
+gg_status gg_make_displacements(const gg_plan* plan, const void* w, int64_t n2_min, int64_t n2_max,
+                                int32_t cic_deconvolve, void* psi, void* work, void* stream);
+
+/* dst (3 fields of n_dst^3) += cloud-in-cell (trilinear, periodic)
+ * interpolation of src (3 fields of n_src^3) to the points m L / n_dst; n_dst
+ * is a multiple of n_src; sums in binary64.  The large-scale half of Eq. 4-5
+ * on the fine lattice. */
+gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream);
+
 /* Per-pass timing of gg_make_ic with HIP events recorded on the call's
  * stream.  Enable before the calls to time; gg_timing_read waits for the last
  * recorded call and returns, for each of the npass passes, the summed

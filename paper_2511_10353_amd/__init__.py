@@ -4,4 +4,5 @@ sqrt(P(k)) i k_j/k^2 filter -> three complex-to-real FFTs -> Zel'dovich
 particles, as hand-written HIP kernels for gfx950 behind the C ABI in
 include/gg.h.  This package holds the in-tree build of that library and its
 ctypes binding."""
-from .binding import Cosmo, GGError, MakeIC, Plan, lib, LIB_PATH, make_ic_autograd  # noqa: F401
+from .binding import (Cosmo, GGError, MakeIC, Plan, lib, LIB_PATH, make_ic_autograd, refine_noise,  # noqa: F401
+                      interpolate_add, cutoff_n2, increase_resolution)

@@ -78,6 +78,10 @@ _SIGS = {
     "gg_make_density": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP]),
     "gg_power_spectrum": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "gg_field_stats": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "gg_refine_noise": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_uint64, ctypes.c_uint32,
+                                        _VP, _VP]),
+    "gg_make_displacements": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP]),
+    "gg_interpolate_add": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
     "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -283,6 +287,17 @@ class Plan:
         _check(lib().gg_field_stats(self._h, _ptr(field), _ptr(out), _ptr(work), _stream()))
         return out
 
+    def make_displacements(self, w, n2_min=0, n2_max=0, deconvolve=False, psi=None, work=None):
+        """psi (3, N, N, N) of the noise w with the mode window n2_min <= n^2 <
+        n2_max (n2_max <= 0: none) and optional CiC deconvolution (Eq. 4-5)."""
+        w = self._need(w, self._real_shape(), self.real_dtype, "w")
+        psi = self._need(psi, (3,) + self._real_shape(), self.real_dtype, "psi")
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_make_displacements(self._h, _ptr(w), int(n2_min), int(n2_max), int(bool(deconvolve)), _ptr(psi),
+                                           _ptr(work), _stream()))
+        return psi
+
     def timing_enable(self, on=True):
         _check(lib().gg_timing_enable(self._h, 1 if on else 0))
 
@@ -291,6 +306,65 @@ class Plan:
         calls = ctypes.c_int(0)
         _check(lib().gg_timing_read(self._h, ms, N_PASSES, ctypes.byref(calls)))
         return [ms[i] for i in range(N_PASSES)], calls.value
+
+
+REFINE_VARIANTS = {"hr": 0, "3": 1, "4": 2, "linear": 3, "sine": 4}
+REFINE_SIZES = {"hr": (1, 2), "3": (2, 3), "4": (2, 4), "linear": (2, 4), "sine": (2, 4)}
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return DTYPES["f32"]
+    if t.dtype == torch.float64:
+        return DTYPES["f64"]
+    raise ValueError("float32 or float64 tensors only")
+
+
+def refine_noise(w_parent, variant="4", seed=0, stream_id=1, out=None):
+    """White-noise refinement (App. A): a (P N_L)^3 parent field -> (P N_H)^3."""
+    if variant not in REFINE_VARIANTS:
+        raise ValueError(f"variant must be one of {sorted(REFINE_VARIANTS)}")
+    n = int(w_parent.shape[0])
+    nl, nh = REFINE_SIZES[variant]
+    nc = n // nl * nh
+    if tuple(w_parent.shape) != (n, n, n) or not w_parent.is_cuda or not w_parent.is_contiguous():
+        raise ValueError("w_parent must be a contiguous cuda tensor (n, n, n)")
+    if out is None:
+        out = torch.empty((nc, nc, nc), dtype=w_parent.dtype, device=w_parent.device)
+    _check(lib().gg_refine_noise(n, _dtype_code(w_parent), REFINE_VARIANTS[variant], _ptr(w_parent), int(seed),
+                                 int(stream_id), _ptr(out), _stream()))
+    return out
+
+
+def interpolate_add(src, dst):
+    """dst (3, n_dst^3) += cloud-in-cell interpolation of src (3, n_src^3)."""
+    if src.dtype != dst.dtype or src.dim() != 4 or dst.dim() != 4 or src.shape[0] != 3 or dst.shape[0] != 3:
+        raise ValueError("src and dst must be (3, n, n, n) tensors of one dtype")
+    _check(lib().gg_interpolate_add(int(src.shape[1]), int(dst.shape[1]), _dtype_code(src), _ptr(src), _ptr(dst),
+                                    _stream()))
+    return dst
+
+
+def cutoff_n2(box, r_s):
+    """The integer mode bound of the top hat f(k r_s) = [k r_s < 1]: n^2 < cutoff."""
+    import math
+    return int(math.ceil((box / (2.0 * math.pi * r_s)) ** 2))
+
+
+def increase_resolution(parent, child, w_parent, variant="4", seed=0, stream_id=1, r_s=None):
+    """Full-box resolution increase (Sec. 2.3): refine the parent noise, take
+    the child's small scales (Eq. 4) and the parent's large scales (Eq. 5,
+    CiC-interpolated with deconvolution).  Returns (w_child, psi_child)."""
+    if r_s is None:
+        r_s = 2.0 * parent.box / parent.n  # two parent cells
+    cut = cutoff_n2(parent.box, r_s)
+    w_child = refine_noise(w_parent, variant, seed, stream_id)
+    if tuple(w_child.shape) != (child.n,) * 3:
+        raise ValueError("child plan size does not match the refined noise")
+    psi = child.make_displacements(w_child, n2_min=cut)
+    large = parent.make_displacements(w_parent, n2_max=cut, deconvolve=True)
+    interpolate_add(large, psi)
+    return w_child, psi
 
 
 class MakeIC(torch.autograd.Function):

@@ -15,6 +15,7 @@
 #include "gg.h"
 #include "diag.h"
 #include "kernels.h"
+#include "refine.h"
 #include "ops.h"
 
 namespace {
@@ -75,6 +76,9 @@ gg::PlanView<T> view(const gg_plan* p) {
     v.tau = static_cast<const T*>(p->tau);
     v.tauseg = static_cast<const float4*>(p->tauseg);
     v.amp_scale = 1.0;
+    v.n2_lo = 0;
+    v.n2_hi = 0x7FFFFFFF;
+    v.deconv = 0;
     return v;
 }
 
@@ -580,6 +584,86 @@ gg_status gg_field_stats(const gg_plan* pc, const void* field, double* out, void
             ? gg::Ops<double>::field_stats(static_cast<const double*>(field), count, out, scratch, nblocks, s)
             : gg::Ops<float>::field_stats(static_cast<const float*>(field), count, out, scratch, nblocks, s);
     return e == hipSuccess ? GG_OK : fail_hip(e, "field_stats launch");
+}
+
+gg_status gg_refine_noise(int32_t n_parent, gg_dtype dtype, gg_refine variant, const void* parent, uint64_t seed,
+                          uint32_t stream_id, void* child, void* stream) {
+    if (!parent || !child) return fail(GG_ERR_INVALID_ARG, "null argument to gg_refine_noise");
+    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    int nl = 0, nh = 0;
+    gg::refine_sizes((int)variant, nl, nh);
+    if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
+    if (n_parent < nl || n_parent % nl || n_parent > 4096)
+        return fail(GG_ERR_INVALID_ARG, "n_parent must be a positive multiple of N_L (at most 4096)");
+    if (!aligned(parent) || !aligned(child)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t es = elem_size(dtype);
+    const size_t nc = (size_t)n_parent / nl * nh;
+    if (overlap(parent, (size_t)n_parent * n_parent * n_parent * es, child, nc * nc * nc * es))
+        return fail(GG_ERR_INVALID_ARG, "parent and child must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = dtype == GG_F64
+                             ? gg::Ops<double>::refine((int)variant, static_cast<const double*>(parent), n_parent, seed,
+                                                       stream_id, static_cast<double*>(child), s)
+                             : gg::Ops<float>::refine((int)variant, static_cast<const float*>(parent), n_parent, seed,
+                                                      stream_id, static_cast<float*>(child), s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "refine launch");
+}
+
+gg_status gg_make_displacements(const gg_plan* pc, const void* w, int64_t n2_min, int64_t n2_max,
+                                int32_t cic_deconvolve, void* psi, void* work, void* stream) {
+    if (!pc || !w || !psi || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_make_displacements");
+    if (n2_min < 0) return fail(GG_ERR_INVALID_ARG, "n2_min must be >= 0");
+    if (!aligned(w) || !aligned(psi) || !aligned(work)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t es = elem_size(pc->dtype);
+    const size_t n3 = (size_t)pc->n * pc->n * pc->n;
+    const size_t wb = gg_workspace_bytes(pc);
+    if (overlap(w, es * n3, work, wb) || overlap(psi, 3 * es * n3, work, wb) || overlap(psi, 3 * es * n3, w, es * n3))
+        return fail(GG_ERR_INVALID_ARG, "w, psi and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    const int64_t big = 0x7FFFFFFF;
+    const int lo = (int)(n2_min < big ? n2_min : big);
+    const int hi = (int)(n2_max <= 0 || n2_max > big ? big : n2_max);
+    gg_plan* p = const_cast<gg_plan*>(pc);
+    gg::ExecCtx x;
+    x.a = static_cast<hipStream_t>(stream);
+    x.b = p->aux;
+    x.sync = p->sync.empty() ? nullptr : p->sync.data();
+    x.nchunk = p->nchunk;
+    hipError_t e;
+    if (p->dtype == GG_F64) {
+        auto v = view<double>(p);
+        v.n2_lo = lo;
+        v.n2_hi = hi;
+        v.deconv = cic_deconvolve ? 1 : 0;
+        e = gg::Ops<double>::make_ic_from_noise(v, static_cast<const double*>(w), nullptr, nullptr, static_cast<double*>(psi),
+                                                static_cast<gg::cx<double>*>(work), x);
+    } else {
+        auto v = view<float>(p);
+        v.n2_lo = lo;
+        v.n2_hi = hi;
+        v.deconv = cic_deconvolve ? 1 : 0;
+        e = gg::Ops<float>::make_ic_from_noise(v, static_cast<const float*>(w), nullptr, nullptr, static_cast<float*>(psi),
+                                               static_cast<gg::cx<float>*>(work), x);
+    }
+    return e == hipSuccess ? GG_OK : fail_hip(e, "make_displacements launch");
+}
+
+gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream) {
+    if (!src || !dst) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add");
+    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    if (n_src < 1 || n_dst < n_src || n_dst % n_src || n_dst > 4096)
+        return fail(GG_ERR_INVALID_ARG, "n_dst must be a multiple of n_src (at most 4096)");
+    if (!aligned(src) || !aligned(dst)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t es = elem_size(dtype);
+    if (overlap(src, 3 * es * n_src * (size_t)n_src * n_src, dst, 3 * es * n_dst * (size_t)n_dst * n_dst))
+        return fail(GG_ERR_INVALID_ARG, "src and dst must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = dtype == GG_F64 ? gg::Ops<double>::cic_add(static_cast<const double*>(src), n_src,
+                                                                   static_cast<double*>(dst), n_dst, s)
+                                         : gg::Ops<float>::cic_add(static_cast<const float*>(src), n_src,
+                                                                  static_cast<float*>(dst), n_dst, s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "interpolate_add launch");
 }
 
 gg_status gg_timing_enable(gg_plan* p, int on) {

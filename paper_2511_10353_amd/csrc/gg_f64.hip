@@ -53,6 +53,17 @@ __global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restr
     if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
+void refine_sizes(int variant, int& nl, int& nh) {
+    switch (variant) {
+        case REFINE_HR: nl = RefineBasis<REFINE_HR>::NL; nh = RefineBasis<REFINE_HR>::NH; break;
+        case REFINE_3: nl = RefineBasis<REFINE_3>::NL; nh = RefineBasis<REFINE_3>::NH; break;
+        case REFINE_4: nl = RefineBasis<REFINE_4>::NL; nh = RefineBasis<REFINE_4>::NH; break;
+        case REFINE_LINEAR: nl = RefineBasis<REFINE_LINEAR>::NL; nh = RefineBasis<REFINE_LINEAR>::NH; break;
+        case REFINE_SINE: nl = RefineBasis<REFINE_SINE>::NL; nh = RefineBasis<REFINE_SINE>::NH; break;
+        default: nl = nh = 0;
+    }
+}
+
 hipError_t launch_dot_final(const double* part, uint32_t count, double scale, double* out, hipStream_t s) {
     k_dot_final<<<1, kDotThreads, 0, s>>>(part, count, scale, out);
     return hipGetLastError();

@@ -43,7 +43,27 @@ struct PlanView {
     const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2, binary64 values rounded to T
     const float4* tauseg;   // piecewise-cubic tau (kTauSeg segments), float plans only
     double amp_scale;       // displacement scale sqrt(A'/A) (1 for the plan's amplitude)
+    // mode window of the axis-0 filter passes (Eq. 4-5): modes with
+    // n2 < n2_lo or n2 >= n2_hi are dropped; deconv divides by the
+    // cloud-in-cell window prod_j sinc^2(pi s_j / N)
+    int n2_lo;
+    int n2_hi;
+    int deconv;
 };
+
+// 1 / sinc^2(pi s / N), the inverse of one axis of the cloud-in-cell window
+template <typename T>
+__device__ inline T cic_deconv(int s, int n) {
+    if (s == 0) return (T)1;
+    const double x = 3.14159265358979323846 * (double)s / (double)n;
+    if constexpr (std::is_same_v<T, float>) {
+        const float xf = (float)x, r = xf / sinf(xf);
+        return r * r;
+    } else {
+        const double r = x / sin(x);
+        return r * r;
+    }
+}
 
 // The filter factor tau(n2) inside the axis-0 passes of the fused path.  The
 // single-precision passes copy the piecewise-cubic table (15 KB) into LDS once
@@ -508,14 +528,16 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         const int s1 = signed_mode(o, N);
         const int s2 = col;
         const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
+        const T dline = pv.deconv ? cic_deconv<T>(s1, N) * cic_deconv<T>(s2, N) : (T)1;
         cx<T> g[V];
 #pragma unroll
         for (int i = 0; i < V; ++i) {
             const int k0 = last_pos<N, -1>(j, i);
             const int s0 = signed_mode(k0, N);
             const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
-            const bool zero = line_zero || (k0 == N / 2);
-            const T tau = taul(zero ? 0 : n2) * (T)pv.amp_scale;  // tau(0) = 0: mean and Nyquist vanish
+            const bool zero = line_zero || (k0 == N / 2) || n2 < pv.n2_lo || n2 >= pv.n2_hi;
+            T tau = taul(zero ? 0 : n2) * (T)pv.amp_scale;  // tau(0) = 0: mean and Nyquist vanish
+            if (pv.deconv) tau *= cic_deconv<T>(s0, N) * dline;
             g[i] = mul_i(cscale(v[i], tau));
             v[i] = cscale(g[i], (T)s0);
         }
@@ -591,14 +613,16 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         const int s2 = col;
         const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
         const T kf = (T)(2.0 * 3.14159265358979323846 / pv.box);
+        const T dline = pv.deconv ? cic_deconv<T>(s1, N) * cic_deconv<T>(s2, N) : (T)1;
         const int jj = opaque(j), cc = opaque(c);
 #pragma unroll
         for (int i = 0; i < V; ++i) {
             const int k0 = last_pos<N, -1>(jj, i);
             const int s0 = signed_mode(k0, N);
             const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
-            const bool zero = line_zero || (k0 == N / 2);
-            const T f = taul(zero ? 0 : n2) * ((T)n2 * kf);
+            const bool zero = line_zero || (k0 == N / 2) || n2 < pv.n2_lo || n2 >= pv.n2_hi;
+            T f = taul(zero ? 0 : n2) * ((T)n2 * kf);
+            if (pv.deconv) f *= cic_deconv<T>(s0, N) * dline;
             v[i] = cscale(v[i], f);
         }
         fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);

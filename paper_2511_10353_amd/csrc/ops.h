@@ -58,6 +58,12 @@ struct Ops {
     // out[0..3] = mean, standard deviation, min, max of count values
     static hipError_t field_stats(const T* field, uint64_t count, double* out, double* scratch, int nblocks,
                                   hipStream_t s);
+    // white-noise refinement (App. A), variant gg_refine value: parent
+    // (n_parent)^3 -> child (n_parent / NL * NH)^3
+    static hipError_t refine(int variant, const T* parent, int n_parent, uint64_t seed, uint32_t stream_id, T* child,
+                             hipStream_t s);
+    // dst (3 fields of n_dst^3) += cloud-in-cell interpolation of src (3 fields of n_src^3)
+    static hipError_t cic_add(const T* src, int n_src, T* dst, int n_dst, hipStream_t s);
     static hipError_t fused_forward(const PlanView<T>& pv, const T* w, uint64_t seed, float* pos, float* vel, T* psi,
                                     cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)
@@ -72,6 +78,9 @@ struct Ops {
     static size_t fused_work_bytes(int n) { return 3 * (size_t)n * n * (n / 2) * sizeof(cx<T>); }
     static size_t inverse_work_bytes(int n) { return (size_t)n * n * (n / 2 + 1) * sizeof(cx<T>); }
 };
+
+// (N_L, N_H) of a refinement variant, or (0, 0) if unknown
+void refine_sizes(int variant, int& nl, int& nh);
 
 // out[0] = scale * sum of part[0..count) in a fixed order (one work-group).
 hipError_t launch_dot_final(const double* part, uint32_t count, double scale, double* out, hipStream_t s);

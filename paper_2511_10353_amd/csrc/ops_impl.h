@@ -4,6 +4,7 @@
 
 #include "cosmo_dev.h"
 #include "diag.h"
+#include "refine.h"
 #include "kernels.h"
 #include "ops.h"
 
@@ -385,6 +386,37 @@ hipError_t Ops<T>::field_stats(const T* field, uint64_t count, double* out, doub
     k_stats_partial<T, true><<<nblocks, kStatThreads, 0, s>>>(field, count, out, scratch);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_stats_final<T, true><<<1, 1, 0, s>>>(scratch, nblocks, count, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Ops<T>::refine(int variant, const T* parent, int n_parent, uint64_t seed, uint32_t stream_id, T* child,
+                          hipStream_t s) {
+    auto run = [&](auto vc) -> hipError_t {
+        constexpr int VAR = decltype(vc)::value;
+        constexpr int NL = RefineBasis<VAR>::NL;
+        if (n_parent < NL || n_parent % NL) return hipErrorInvalidValue;
+        const int P = n_parent / NL;
+        const uint64_t np = (uint64_t)P * P * P;
+        k_refine<T, VAR><<<(unsigned)((np + kRefineThreads - 1) / kRefineThreads), kRefineThreads, 0, s>>>(
+            parent, P, seed, stream_id, child);
+        return hipGetLastError();
+    };
+    switch (variant) {
+        case REFINE_HR: return run(std::integral_constant<int, REFINE_HR>{});
+        case REFINE_3: return run(std::integral_constant<int, REFINE_3>{});
+        case REFINE_4: return run(std::integral_constant<int, REFINE_4>{});
+        case REFINE_LINEAR: return run(std::integral_constant<int, REFINE_LINEAR>{});
+        case REFINE_SINE: return run(std::integral_constant<int, REFINE_SINE>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Ops<T>::cic_add(const T* src, int n_src, T* dst, int n_dst, hipStream_t s) {
+    if (n_src < 1 || n_dst < n_src || n_dst % n_src) return hipErrorInvalidValue;
+    const uint64_t n3 = (uint64_t)n_dst * n_dst * n_dst;
+    k_cic_add<T><<<dim3(capped_grid(n3, 256), 3), 256, 0, s>>>(src, n_src, n_dst / n_src, dst);
     return hipGetLastError();
 }
 
