@@ -9,8 +9,8 @@
 // rows (the contiguous copies of the z passes) hits every LDS bank once.
 //
 // Thread t of the group works on line c = t % L as the j = t / L-th of
-// TPL = M / RMAX threads of that line; it holds RMAX complex values in
-// registers.  A stage of radix R with sub-length NS (product of the radices
+// TPL = M / V threads of that line; it holds V complex values in registers
+// (V a multiple of every radix of the line's plan).  A stage of radix R with sub-length NS (product of the radices
 // already applied) performs, for butterfly b in [0, M/R), k = b mod NS:
 //   a_r = x[b + r M/R] * W_{NS R}^{r k},  A = DFT_R(a),
 //   y[(b - k) R + k + r NS] = A_r,
@@ -128,10 +128,46 @@ __device__ __forceinline__ void dft16(cx<T>* a) {
 #undef GG_SWAP
 }
 
+// radix 3: w = exp(DIR 2 pi i / 3) = -1/2 + DIR i sqrt(3)/2
+constexpr double kSqrt3Half = 0.86602540378443864676;
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3(cx<T>* a) {
+    const cx<T> t = cadd(a[1], a[2]);
+    const cx<T> d = cscale(rot90<DIR>(csub(a[1], a[2])), (T)kSqrt3Half);
+    const cx<T> m = csub(a[0], cscale(t, (T)0.5));
+    a[0] = cadd(a[0], t);
+    a[1] = cadd(m, d);
+    a[2] = csub(m, d);
+}
+
+// radix 5: c1 = cos(2 pi/5), c2 = cos(4 pi/5), s1 = sin(2 pi/5), s2 = sin(4 pi/5)
+constexpr double kC51 = 0.30901699437494742410;
+constexpr double kC52 = -0.80901699437494742410;
+constexpr double kS51 = 0.95105651629515357212;
+constexpr double kS52 = 0.58778525229247312917;
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft5(cx<T>* a) {
+    const cx<T> t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const cx<T> d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+    const cx<T> m1 = cadd(a[0], cadd(cscale(t1, (T)kC51), cscale(t2, (T)kC52)));
+    const cx<T> m2 = cadd(a[0], cadd(cscale(t1, (T)kC52), cscale(t2, (T)kC51)));
+    const cx<T> r1 = rot90<DIR>(cadd(cscale(d1, (T)kS51), cscale(d2, (T)kS52)));
+    const cx<T> r2 = rot90<DIR>(csub(cscale(d1, (T)kS52), cscale(d2, (T)kS51)));
+    a[0] = cadd(a[0], cadd(t1, t2));
+    a[1] = cadd(m1, r1);
+    a[4] = csub(m1, r1);
+    a[2] = cadd(m2, r2);
+    a[3] = csub(m2, r2);
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* a) {
     if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
+    else if constexpr (R == 3) dft3<DIR>(a);
     else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+    else if constexpr (R == 5) dft5<DIR>(a);
     else if constexpr (R == 8) dft8<DIR>(a);
     else if constexpr (R == 16) dft16<DIR>(a);
     else static_assert(R == 2, "unsupported radix");
@@ -142,27 +178,39 @@ __device__ __forceinline__ void dft(cx<T>* a) {
 // applies them in reverse order so that its first stage reads the positions
 // the forward's last stage leaves in registers).
 // ---------------------------------------------------------------------------
+// V: complex values per thread (every radix of the plan divides it); a
+// thread performs V / R butterflies of each radix-R stage.  The mixed-radix
+// plans serve the uneven lattices (N = 96, 160, 192 and their r2c halves).
 template <int M> struct Plan;
-template <> struct Plan<4>    { static constexpr int S = 1; static constexpr int R[1] = {4}; };
-template <> struct Plan<8>    { static constexpr int S = 1; static constexpr int R[1] = {8}; };
-template <> struct Plan<16>   { static constexpr int S = 1; static constexpr int R[1] = {16}; };
-template <> struct Plan<32>   { static constexpr int S = 2; static constexpr int R[2] = {8, 4}; };
-template <> struct Plan<64>   { static constexpr int S = 2; static constexpr int R[2] = {8, 8}; };
-template <> struct Plan<128>  { static constexpr int S = 2; static constexpr int R[2] = {16, 8}; };
-template <> struct Plan<256>  { static constexpr int S = 2; static constexpr int R[2] = {16, 16}; };
-template <> struct Plan<512>  { static constexpr int S = 3; static constexpr int R[3] = {8, 8, 8}; };
-template <> struct Plan<1024> { static constexpr int S = 3; static constexpr int R[3] = {16, 4, 16}; };
+template <> struct Plan<4>    { static constexpr int S = 1, V = 4;  static constexpr int R[1] = {4}; };
+template <> struct Plan<8>    { static constexpr int S = 1, V = 8;  static constexpr int R[1] = {8}; };
+template <> struct Plan<16>   { static constexpr int S = 1, V = 16; static constexpr int R[1] = {16}; };
+template <> struct Plan<32>   { static constexpr int S = 2, V = 8;  static constexpr int R[2] = {8, 4}; };
+template <> struct Plan<48>   { static constexpr int S = 3, V = 12; static constexpr int R[3] = {4, 4, 3}; };
+template <> struct Plan<64>   { static constexpr int S = 2, V = 8;  static constexpr int R[2] = {8, 8}; };
+template <> struct Plan<80>   { static constexpr int S = 3, V = 20; static constexpr int R[3] = {4, 4, 5}; };
+template <> struct Plan<96>   { static constexpr int S = 3, V = 24; static constexpr int R[3] = {8, 4, 3}; };
+template <> struct Plan<128>  { static constexpr int S = 2, V = 16; static constexpr int R[2] = {16, 8}; };
+template <> struct Plan<160>  { static constexpr int S = 4, V = 20; static constexpr int R[4] = {4, 4, 2, 5}; };
+template <> struct Plan<192>  { static constexpr int S = 3, V = 24; static constexpr int R[3] = {8, 8, 3}; };
+template <> struct Plan<256>  { static constexpr int S = 2, V = 16; static constexpr int R[2] = {16, 16}; };
+template <> struct Plan<512>  { static constexpr int S = 3, V = 8;  static constexpr int R[3] = {8, 8, 8}; };
+template <> struct Plan<1024> { static constexpr int S = 3, V = 16; static constexpr int R[3] = {16, 4, 16}; };
 
 template <int M>
 struct PlanInfo {
-    static constexpr int rmax() {
-        int r = 0;
-        for (int s = 0; s < Plan<M>::S; ++s) r = Plan<M>::R[s] > r ? Plan<M>::R[s] : r;
-        return r;
+    static constexpr bool valid() {
+        int prod = 1;
+        for (int s = 0; s < Plan<M>::S; ++s) {
+            if (Plan<M>::V % Plan<M>::R[s] != 0) return false;
+            prod *= Plan<M>::R[s];
+        }
+        return prod == M && M % Plan<M>::V == 0;
     }
-    static constexpr int RMAX = rmax();
-    static constexpr int TPL = M / RMAX;  // threads per line
-    static constexpr int V = RMAX;        // complex values held per thread
+    static_assert(valid(), "radices must multiply to M and divide V");
+    static constexpr int V = Plan<M>::V;   // complex values held per thread
+    static constexpr int RMAX = V;
+    static constexpr int TPL = M / V;      // threads per line
     template <int DIR>
     static constexpr int first_radix() { return DIR < 0 ? Plan<M>::R[0] : Plan<M>::R[Plan<M>::S - 1]; }
     template <int DIR>
@@ -201,7 +249,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, cx<T>* lds, const cx<T>
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
         const int b = j + TPL * u;
-        const int k = b & (NS - 1);
+        const int k = (int)((unsigned)b % (unsigned)NS);
         if constexpr (!FIRST) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {

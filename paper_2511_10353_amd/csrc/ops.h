@@ -11,9 +11,11 @@ namespace gg {
 template <typename T>
 struct PlanView;
 
-// Lattice sizes the kernels are instantiated for.
+// Lattice sizes the kernels are instantiated for: powers of two, and the
+// uneven sizes 96 = 2^5 3, 160 = 2^5 5, 192 = 2^6 3 (mixed-radix plans).
 constexpr bool supported_n(int n) {
-    return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024;
+    return n == 8 || n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 160 || n == 192 || n == 256 ||
+           n == 512 || n == 1024;
 }
 
 // Launch context of the fused path.  With nchunk > 1 and an auxiliary stream,

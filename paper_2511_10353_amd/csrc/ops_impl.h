@@ -17,7 +17,10 @@ hipError_t dispatch_n(int n, F&& f) {
         case 16: return f(std::integral_constant<int, 16>{});
         case 32: return f(std::integral_constant<int, 32>{});
         case 64: return f(std::integral_constant<int, 64>{});
+        case 96: return f(std::integral_constant<int, 96>{});
         case 128: return f(std::integral_constant<int, 128>{});
+        case 160: return f(std::integral_constant<int, 160>{});
+        case 192: return f(std::integral_constant<int, 192>{});
         case 256: return f(std::integral_constant<int, 256>{});
         case 512: return f(std::integral_constant<int, 512>{});
         case 1024: return f(std::integral_constant<int, 1024>{});

@@ -80,7 +80,7 @@ def _create(lib, n=32, box=100.0, dtype=0, **kw):
     return st, lib.gg_last_error().decode()
 
 
-@pytest.mark.parametrize("n", [0, 7, 12, 48, 2048, -8])
+@pytest.mark.parametrize("n", [0, 7, 12, 48, 100, 2048, -8])
 def test_unsupported_sizes_rejected(lib, n):
     st, msg = _create(lib, n=n)
     assert st == 2 and "power of two" in msg

@@ -69,7 +69,7 @@ def test_noise_bit_exact_sampled_1024():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 96, 128, 160, 192, 256])
 def test_fft_forward(n, dtype):
     p = _plan(n, 100.0, dtype)
     x = inputs.real_field(n, 100 + n, NPDT[dtype])
@@ -81,7 +81,7 @@ def test_fft_forward(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 96, 128, 160, 192, 256])
 def test_fft_inverse(n, dtype):
     p = _plan(n, 100.0, dtype)
     x = inputs.real_field(n, 200 + n, np.float64)
@@ -96,7 +96,7 @@ def test_fft_inverse(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("n", [16, 64])
+@pytest.mark.parametrize("n", [16, 64, 96])
 def test_filter(n, dtype):
     box = 100.0
     p = _plan(n, box, dtype)
@@ -158,6 +158,8 @@ def _check_ic(n, box, seed, dtype, pos, vel, psi):
 
 
 @pytest.mark.parametrize("n,box,dtype", [(32, 100.0, "f64"), (32, 100.0, "f32"), (64, 100.0, "f32"),
+                                         (96, 112.5, "f32"), (96, 112.5, "f64"), (160, 46.875, "f32"),
+                                         (160, 46.875, "f64"), (192, 112.5, "f32"), (192, 112.5, "f64"),
                                          (256, 500.0, "f32"), (256, 500.0, "f64")])
 def test_make_ic_vs_oracle(n, box, dtype):
     p = _plan(n, box, dtype)
