@@ -16,7 +16,8 @@ every level:
              W_CiC, inverse transformed, then cloud-in-cell interpolated to the
              level's lattice points o_l Delta_{l-1} + m Delta_l;
   psi        small + large; particles at O_l + (m + 1/2) Delta_l + psi,
-             wrapped into [0, L_0), O_l the level's origin in the base box.
+             wrapped into [0, L_0), O_l the level's origin in the base box
+             (itself taken into [0, L_0)).
 
 The periodic transform inside a sub-box makes psi deviate from the field of a
 full-box high-resolution realisation with the same noise; the paper puts the
@@ -120,7 +121,7 @@ def hierarchy(n0, box0, sizes, origins, seed, cosmo, workers=None):
         box = n * cell
         w = refine.refine(periodic_slice(par["w"], o, n // 2), "4", seed, lev)
         psi = level_displacements(w, n, box, par["psi"], par["n"], par["box"], o, cosmo, workers=workers)
-        origin_box = tuple(par["origin_box"][j] + o[j] * par["cell"] for j in range(3))
+        origin_box = tuple(float(np.fmod(par["origin_box"][j] + o[j] * par["cell"], box0)) for j in range(3))
         pos, vel = particles(psi, n, cell, origin_box, box0, cosmo)
         levels.append(dict(n=n, box=box, cell=cell, origin_box=origin_box, w=w, psi=psi, pos=pos, vel=vel))
     return levels

@@ -65,7 +65,7 @@ def test_small_hierarchy_shapes_and_nesting():
     levels = zoom.hierarchy(32, 60.0, [32, 24], [(4, 20, 30), (8, 8, 10)], seed=7, cosmo=COSMO)
     assert [lv["n"] for lv in levels] == [32, 32, 24]
     assert levels[1]["cell"] == 60.0 / 64 and levels[2]["cell"] == 60.0 / 128
-    assert levels[2]["origin_box"] == tuple(levels[1]["origin_box"][j] + o * levels[1]["cell"]
+    assert levels[2]["origin_box"] == tuple(float(np.fmod(levels[1]["origin_box"][j] + o * levels[1]["cell"], 60.0))
                                             for j, o in enumerate((8, 8, 10)))
     for lv in levels:
         assert lv["pos"].min() >= 0 and lv["pos"].max() < 60.0
