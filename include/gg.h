@@ -72,8 +72,8 @@ typedef enum {
 
 typedef enum { GG_F32 = 0, GG_F64 = 1 } gg_dtype;
 
-/* Lattice: N cells per side (a power of two, 8 <= N <= 1024), box side L in
- * Mpc/h. */
+/* Lattice: N cells per side (a power of two, 8 <= N <= 1024, or 96, 160,
+ * 192), box side L in Mpc/h. */
 typedef struct {
     int32_t n;
     double box;
@@ -228,6 +228,14 @@ typedef enum { GG_REFINE_HR = 0, GG_REFINE_3 = 1, GG_REFINE_4 = 2, GG_REFINE_LIN
 gg_status gg_refine_noise(int32_t n_parent, gg_dtype dtype, gg_refine variant, const void* parent, uint64_t seed,
                           uint32_t stream_id, void* child, void* stream);
 
+/* The same refinement restricted to a sub-box of the parent: the parent cells
+ * origin[j] + [0, count) per axis (periodic in the n_parent^3 parent); count
+ * a multiple of N_L; child (count / N_L * N_H)^3.  Patches are numbered
+ * row-major over the sub-box.  The noise of a zoom level (Sec. 2.4). */
+gg_status gg_refine_noise_region(int32_t n_parent, const int32_t origin[3], int32_t count, gg_dtype dtype,
+                                 gg_refine variant, const void* parent, uint64_t seed, uint32_t stream_id, void* child,
+                                 void* stream);
+
 /* Displacements psi (3 R arrays, plan dtype) of the noise field w (R) with
  * the filter restricted to a window of modes, for combining two resolutions
  * (Eq. 4-5): modes with n^2 < n2_min or n^2 >= n2_max are dropped (n2_max
@@ -244,6 +252,64 @@ gg_status gg_make_displacements(const gg_plan* plan, const void* w, int64_t n2_m
  * is a multiple of n_src; sums in binary64.  The large-scale half of Eq. 4-5
  * on the fine lattice. */
 gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream);
+
+/* dst (3 fields of n_dst^3) += cloud-in-cell interpolation of the periodic
+ * src (3 fields of n_src^3) at the points origin + m / ratio (in src cells,
+ * m < n_dst per axis): the large-scale half of Eq. 4-5 for a zoom level whose
+ * sub-box starts at src cell `origin` and refines it by `ratio`. */
+gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t origin[3], int32_t n_dst, gg_dtype dtype,
+                                const void* src, void* dst, void* stream);
+
+/* Eq. 5 on a real periodic field (R, plan dtype): its transform restricted to
+ * n^2 < n2_max (n2_max <= 0: no bound), divided by the cloud-in-cell window
+ * if cic_deconvolve is set, transformed back into out (R; may equal field).
+ * work: gg_workspace_bytes(plan). */
+gg_status gg_lowpass(const gg_plan* plan, const void* field, int64_t n2_max, int32_t cic_deconvolve, void* out,
+                     void* work, void* stream);
+
+/* Eq. (3) for a lattice placed at origin (3 doubles, Mpc/h) inside a larger
+ * periodic box: x_j = wrap(origin_j + (m_j + lattice_offset) L/N + psi_j) into
+ * [0, wrap_box), velocities a H f psi_j.  A zoom level's particles in the base
+ * box (L is the plan's sub-box side). */
+gg_status gg_zeldovich_at(const gg_plan* plan, const void* psi, const double origin[3], double wrap_box, float* pos,
+                          float* vel, void* stream);
+
+/* Zoom hierarchy (Sec. 2.3-2.4): a base lattice n[0]^3 over the periodic box
+ * L_0 and levels l = 1 .. levels-1 of n[l]^3 cells, each halving its parent's
+ * cell over a sub-box of n[l]/2 parent cells starting at parent cell
+ * origin[l] (level 1 may wrap around the base box; deeper levels must lie
+ * inside their parent sub-box).  Per level: noise = App. A refinement of the
+ * parent's sub-box noise (basis `variant`, stream_id = l; the base level is
+ * the noise of `seed`, stream 0); psi = Eq. 4 on the level's periodic sub-box
+ * (r_s = 2 parent cells) + the CiC interpolation of Eq. 5 applied to the
+ * parent's psi (with deconvolution); particles at the level's lattice inside
+ * the base box (Eq. 3, positions wrapped into [0, L_0)). */
+#define GG_ZOOM_MAX_LEVELS 8
+typedef struct {
+    int32_t levels;
+    int32_t n[GG_ZOOM_MAX_LEVELS];
+    int32_t origin[GG_ZOOM_MAX_LEVELS][3];  /* entry 0 unused */
+    double box;                              /* L_0 */
+    int32_t variant;                         /* gg_refine with N_H = 2 N_L */
+} gg_zoom_desc;
+
+typedef struct gg_zoom gg_zoom;
+
+/* Creates one plan per level (sub-box side n[l] L_0 / (n[0] 2^l)); synchronous. */
+gg_status gg_zoom_create(gg_zoom** zoom, const gg_zoom_desc* desc, const gg_cosmo* cosmo, gg_dtype dtype);
+gg_status gg_zoom_destroy(gg_zoom* zoom);
+size_t gg_zoom_workspace_bytes(const gg_zoom* zoom);
+/* Level geometry: sub-box side, cell size and origin in the base box (Mpc/h). */
+gg_status gg_zoom_query(const gg_zoom* zoom, int32_t level, double* box, double* cell, double origin[3]);
+
+/* Runs the whole hierarchy on `stream`.  w[l] (R of level l), psi[l] (3 R),
+ * pos[l] and vel[l] (3 n[l]^3 floats) are host arrays of device pointers, one
+ * per level; work: gg_zoom_workspace_bytes.  With use_graph set, the launch
+ * sequence is captured into a HIP graph on the first call (stream must not be
+ * NULL) and replayed as one graph launch while seed and pointers stay the
+ * same (captured again otherwise).  Calls on one zoom must not overlap. */
+gg_status gg_zoom_run(gg_zoom* zoom, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
+                      float* const* vel, void* work, int32_t use_graph, void* stream);
 
 /* Per-pass timing of gg_make_ic with HIP events recorded on the call's
  * stream.  Enable before the calls to time; gg_timing_read waits for the last

@@ -82,6 +82,17 @@ _SIGS = {
                                         _VP, _VP]),
     "gg_make_displacements": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP]),
     "gg_interpolate_add": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
+    "gg_refine_noise_region": (ctypes.c_int, [ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, _VP,
+                                               ctypes.c_uint64, ctypes.c_uint32, _VP, _VP]),
+    "gg_interpolate_add_at": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int, _VP, _VP,
+                                              _VP]),
+    "gg_lowpass": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP]),
+    "gg_zeldovich_at": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP]),
+    "gg_zoom_create": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
+    "gg_zoom_destroy": (ctypes.c_int, [_VP]),
+    "gg_zoom_workspace_bytes": (ctypes.c_size_t, [_VP]),
+    "gg_zoom_query": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "gg_zoom_run": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
     "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -298,6 +309,25 @@ class Plan:
                                            _ptr(work), _stream()))
         return psi
 
+    def lowpass(self, field, n2_max, deconvolve=True, out=None, work=None):
+        """Eq. 5 on a real field: modes n^2 < n2_max kept (optionally / W_CiC)."""
+        field = self._need(field, self._real_shape(), self.real_dtype, "field")
+        out = self._need(out, self._real_shape(), self.real_dtype, "out")
+        if work is None:
+            work = self.workspace()
+        _check(lib().gg_lowpass(self._h, _ptr(field), int(n2_max), int(bool(deconvolve)), _ptr(out), _ptr(work),
+                                _stream()))
+        return out
+
+    def zeldovich_at(self, psi, origin, wrap_box, pos=None, vel=None):
+        """Eq. 3 for this plan's lattice placed at ``origin`` inside a periodic box."""
+        psi = self._need(psi, (3,) + self._real_shape(), self.real_dtype, "psi")
+        pos = self._need(pos, (3,) + self._real_shape(), torch.float32, "pos")
+        vel = self._need(vel, (3,) + self._real_shape(), torch.float32, "vel")
+        o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+        _check(lib().gg_zeldovich_at(self._h, _ptr(psi), o, float(wrap_box), _ptr(pos), _ptr(vel), _stream()))
+        return pos, vel
+
     def timing_enable(self, on=True):
         _check(lib().gg_timing_enable(self._h, 1 if on else 0))
 
@@ -334,6 +364,89 @@ def refine_noise(w_parent, variant="4", seed=0, stream_id=1, out=None):
     _check(lib().gg_refine_noise(n, _dtype_code(w_parent), REFINE_VARIANTS[variant], _ptr(w_parent), int(seed),
                                  int(stream_id), _ptr(out), _stream()))
     return out
+
+
+def refine_noise_region(w_parent, origin, count, variant="4", seed=0, stream_id=1, out=None):
+    """App. A refinement of the parent cells origin + [0, count) (periodic)."""
+    n = int(w_parent.shape[0])
+    nl, nh = REFINE_SIZES[variant]
+    nc = count // nl * nh
+    if out is None:
+        out = torch.empty((nc, nc, nc), dtype=w_parent.dtype, device=w_parent.device)
+    o = (ctypes.c_int32 * 3)(*[int(v) for v in origin])
+    _check(lib().gg_refine_noise_region(n, o, int(count), _dtype_code(w_parent), REFINE_VARIANTS[variant],
+                                        _ptr(w_parent), int(seed), int(stream_id), _ptr(out), _stream()))
+    return out
+
+
+def interpolate_add_at(src, dst, origin, ratio=2):
+    """dst (3, n_dst^3) += CiC interpolation of src at origin + m / ratio (src cells)."""
+    o = (ctypes.c_int32 * 3)(*[int(v) for v in origin])
+    _check(lib().gg_interpolate_add_at(int(src.shape[1]), int(ratio), o, int(dst.shape[1]), _dtype_code(src), _ptr(src),
+                                       _ptr(dst), _stream()))
+    return dst
+
+
+class _ZoomDesc(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("n", ctypes.c_int32 * 8), ("origin", (ctypes.c_int32 * 3) * 8),
+                ("box", ctypes.c_double), ("variant", ctypes.c_int32)]
+
+
+class Zoom:
+    """A zoom hierarchy: base lattice n0^3 over ``box`` plus nested levels of
+    ``sizes`` at origins (parent cells); buffers are allocated once and reused."""
+
+    def __init__(self, n0, box, sizes, origins, cosmo=None, dtype="f32", variant="4"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgg needs a ROCm GPU; torch.cuda.is_available() is False")
+        torch.cuda.init()
+        self.ns = [int(n0)] + [int(v) for v in sizes]
+        self.box = float(box)
+        self.dtype = dtype
+        self.real_dtype = torch.float32 if dtype == "f32" else torch.float64
+        d = _ZoomDesc()
+        d.levels = len(self.ns)
+        for l, n in enumerate(self.ns):
+            d.n[l] = n
+        for l, o in enumerate(origins, start=1):
+            for a in range(3):
+                d.origin[l][a] = int(o[a])
+        d.box = self.box
+        d.variant = REFINE_VARIANTS[variant]
+        self._h = ctypes.c_void_p()
+        _check(lib().gg_zoom_create(ctypes.byref(self._h), ctypes.byref(d), ctypes.byref((cosmo or Cosmo())._c()),
+                                    DTYPES[dtype]))
+        self.geometry = []
+        for l in range(len(self.ns)):
+            b, c, o = ctypes.c_double(), ctypes.c_double(), (ctypes.c_double * 3)()
+            _check(lib().gg_zoom_query(self._h, l, ctypes.byref(b), ctypes.byref(c), o))
+            self.geometry.append(dict(box=b.value, cell=c.value, origin=tuple(o)))
+        self.work = torch.empty(int(lib().gg_zoom_workspace_bytes(self._h)), dtype=torch.uint8, device="cuda")
+        self.levels = []
+        for n in self.ns:
+            self.levels.append(dict(
+                w=torch.empty((n, n, n), dtype=self.real_dtype, device="cuda"),
+                psi=torch.empty((3, n, n, n), dtype=self.real_dtype, device="cuda"),
+                pos=torch.empty((3, n, n, n), dtype=torch.float32, device="cuda"),
+                vel=torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")))
+        self._ptrs = {k: (ctypes.c_void_p * len(self.ns))(*[lv[k].data_ptr() for lv in self.levels])
+                      for k in ("w", "psi", "pos", "vel")}
+
+    def run(self, seed, use_graph=False):
+        _check(lib().gg_zoom_run(self._h, int(seed), self._ptrs["w"], self._ptrs["psi"], self._ptrs["pos"],
+                                 self._ptrs["vel"], _ptr(self.work), int(bool(use_graph)), _stream()))
+        return self.levels
+
+    def close(self):
+        if self._h:
+            lib().gg_zoom_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def interpolate_add(src, dst):

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -79,6 +81,8 @@ gg::PlanView<T> view(const gg_plan* p) {
     v.n2_lo = 0;
     v.n2_hi = 0x7FFFFFFF;
     v.deconv = 0;
+    v.origin[0] = v.origin[1] = v.origin[2] = 0.0;
+    v.wrap = p->box;
     return v;
 }
 
@@ -157,7 +161,8 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     if (!out || !grid || !cosmo) return fail(GG_ERR_INVALID_ARG, "null argument to gg_plan_create");
     if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "dtype must be GG_F32 or GG_F64");
     if (!gg::supported_n(grid->n))
-        return fail(GG_ERR_UNSUPPORTED_SIZE, "N must be a power of two in [8, 1024], got " + std::to_string(grid->n));
+        return fail(GG_ERR_UNSUPPORTED_SIZE,
+                    "N must be a power of two in [8, 1024] or one of 96, 160, 192, got " + std::to_string(grid->n));
     const gg_cosmo& c = *cosmo;
     if (!(grid->box > 0) || !std::isfinite(grid->box)) return fail(GG_ERR_INVALID_ARG, "box must be > 0");
     if (!(c.omega_m > 0 && c.omega_m <= 1)) return fail(GG_ERR_INVALID_ARG, "omega_m must be in (0, 1]");
@@ -586,27 +591,42 @@ gg_status gg_field_stats(const gg_plan* pc, const void* field, double* out, void
     return e == hipSuccess ? GG_OK : fail_hip(e, "field_stats launch");
 }
 
-gg_status gg_refine_noise(int32_t n_parent, gg_dtype dtype, gg_refine variant, const void* parent, uint64_t seed,
-                          uint32_t stream_id, void* child, void* stream) {
-    if (!parent || !child) return fail(GG_ERR_INVALID_ARG, "null argument to gg_refine_noise");
+gg_status gg_refine_noise_region(int32_t n_parent, const int32_t origin[3], int32_t count, gg_dtype dtype,
+                                 gg_refine variant, const void* parent, uint64_t seed, uint32_t stream_id, void* child,
+                                 void* stream) {
+    if (!parent || !child || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_refine_noise_region");
     if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
     int nl = 0, nh = 0;
     gg::refine_sizes((int)variant, nl, nh);
     if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
-    if (n_parent < nl || n_parent % nl || n_parent > 4096)
-        return fail(GG_ERR_INVALID_ARG, "n_parent must be a positive multiple of N_L (at most 4096)");
+    if (n_parent < 1 || n_parent > 4096) return fail(GG_ERR_INVALID_ARG, "n_parent must be in [1, 4096]");
+    if (count < nl || count % nl || count > n_parent)
+        return fail(GG_ERR_INVALID_ARG, "count must be a positive multiple of N_L, at most n_parent");
+    for (int a = 0; a < 3; ++a)
+        if (origin[a] < 0 || origin[a] >= n_parent) return fail(GG_ERR_INVALID_ARG, "origin must be in [0, n_parent)");
     if (!aligned(parent) || !aligned(child)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
     const size_t es = elem_size(dtype);
-    const size_t nc = (size_t)n_parent / nl * nh;
+    const size_t nc = (size_t)count / nl * nh;
     if (overlap(parent, (size_t)n_parent * n_parent * n_parent * es, child, nc * nc * nc * es))
         return fail(GG_ERR_INVALID_ARG, "parent and child must not overlap");
+    const int o[3] = {origin[0], origin[1], origin[2]};
     hipStream_t s = static_cast<hipStream_t>(stream);
     const hipError_t e = dtype == GG_F64
-                             ? gg::Ops<double>::refine((int)variant, static_cast<const double*>(parent), n_parent, seed,
-                                                       stream_id, static_cast<double*>(child), s)
-                             : gg::Ops<float>::refine((int)variant, static_cast<const float*>(parent), n_parent, seed,
-                                                      stream_id, static_cast<float*>(child), s);
+                             ? gg::Ops<double>::refine((int)variant, static_cast<const double*>(parent), n_parent, o,
+                                                       count, seed, stream_id, static_cast<double*>(child), s)
+                             : gg::Ops<float>::refine((int)variant, static_cast<const float*>(parent), n_parent, o, count,
+                                                      seed, stream_id, static_cast<float*>(child), s);
     return e == hipSuccess ? GG_OK : fail_hip(e, "refine launch");
+}
+
+gg_status gg_refine_noise(int32_t n_parent, gg_dtype dtype, gg_refine variant, const void* parent, uint64_t seed,
+                          uint32_t stream_id, void* child, void* stream) {
+    int nl = 0, nh = 0;
+    gg::refine_sizes((int)variant, nl, nh);
+    if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
+    if (n_parent < nl || n_parent % nl) return fail(GG_ERR_INVALID_ARG, "n_parent must be a positive multiple of N_L");
+    const int32_t origin[3] = {0, 0, 0};
+    return gg_refine_noise_region(n_parent, origin, n_parent, dtype, variant, parent, seed, stream_id, child, stream);
 }
 
 gg_status gg_make_displacements(const gg_plan* pc, const void* w, int64_t n2_min, int64_t n2_max,
@@ -649,21 +669,82 @@ gg_status gg_make_displacements(const gg_plan* pc, const void* w, int64_t n2_min
     return e == hipSuccess ? GG_OK : fail_hip(e, "make_displacements launch");
 }
 
-gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream) {
-    if (!src || !dst) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add");
+gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t origin[3], int32_t n_dst, gg_dtype dtype,
+                                const void* src, void* dst, void* stream) {
+    if (!src || !dst || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add_at");
     if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
-    if (n_src < 1 || n_dst < n_src || n_dst % n_src || n_dst > 4096)
-        return fail(GG_ERR_INVALID_ARG, "n_dst must be a multiple of n_src (at most 4096)");
+    if (n_src < 1 || n_src > 4096 || n_dst < 1 || n_dst > 4096 || ratio < 1 || ratio > 64)
+        return fail(GG_ERR_INVALID_ARG, "sizes in [1, 4096], ratio in [1, 64]");
+    for (int a = 0; a < 3; ++a)
+        if (origin[a] < 0 || origin[a] >= n_src) return fail(GG_ERR_INVALID_ARG, "origin must be in [0, n_src)");
     if (!aligned(src) || !aligned(dst)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
     const size_t es = elem_size(dtype);
     if (overlap(src, 3 * es * n_src * (size_t)n_src * n_src, dst, 3 * es * n_dst * (size_t)n_dst * n_dst))
         return fail(GG_ERR_INVALID_ARG, "src and dst must not overlap");
+    const int o[3] = {origin[0], origin[1], origin[2]};
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t e = dtype == GG_F64 ? gg::Ops<double>::cic_add(static_cast<const double*>(src), n_src,
+    const hipError_t e = dtype == GG_F64 ? gg::Ops<double>::cic_add(static_cast<const double*>(src), n_src, ratio, o,
                                                                    static_cast<double*>(dst), n_dst, s)
-                                         : gg::Ops<float>::cic_add(static_cast<const float*>(src), n_src,
+                                         : gg::Ops<float>::cic_add(static_cast<const float*>(src), n_src, ratio, o,
                                                                   static_cast<float*>(dst), n_dst, s);
     return e == hipSuccess ? GG_OK : fail_hip(e, "interpolate_add launch");
+}
+
+gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream) {
+    if (n_src < 1 || n_dst < n_src || n_dst % n_src)
+        return fail(GG_ERR_INVALID_ARG, "n_dst must be a multiple of n_src");
+    const int32_t origin[3] = {0, 0, 0};
+    return gg_interpolate_add_at(n_src, n_dst / n_src, origin, n_dst, dtype, src, dst, stream);
+}
+
+gg_status gg_lowpass(const gg_plan* pc, const void* field, int64_t n2_max, int32_t cic_deconvolve, void* out, void* work,
+                     void* stream) {
+    if (!pc || !field || !out || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_lowpass");
+    if (!aligned(field) || !aligned(out) || !aligned(work)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t rb = (size_t)pc->n * pc->n * pc->n * elem_size(pc->dtype);
+    const size_t wb = gg_workspace_bytes(pc);
+    if (overlap(field, rb, work, wb) || overlap(out, rb, work, wb))
+        return fail(GG_ERR_INVALID_ARG, "field, out and work must not overlap (field may equal out)");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    const int hi = (int)(n2_max <= 0 || n2_max > 0x7FFFFFFF ? 0x7FFFFFFF : n2_max);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e =
+        pc->dtype == GG_F64
+            ? gg::Ops<double>::lowpass(view<double>(pc), static_cast<const double*>(field), hi, cic_deconvolve ? 1 : 0,
+                                       static_cast<double*>(out), static_cast<gg::cx<double>*>(work), s)
+            : gg::Ops<float>::lowpass(view<float>(pc), static_cast<const float*>(field), hi, cic_deconvolve ? 1 : 0,
+                                      static_cast<float*>(out), static_cast<gg::cx<float>*>(work), s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "lowpass launch");
+}
+
+gg_status gg_zeldovich_at(const gg_plan* pc, const void* psi, const double origin[3], double wrap_box, float* pos,
+                          float* vel, void* stream) {
+    if (!pc || !psi || !pos || !vel || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zeldovich_at");
+    if (!(wrap_box > 0) || !std::isfinite(wrap_box)) return fail(GG_ERR_INVALID_ARG, "wrap_box must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!(origin[a] >= 0 && origin[a] < wrap_box)) return fail(GG_ERR_INVALID_ARG, "origin must be in [0, wrap_box)");
+    if (!aligned(psi) || !aligned(pos) || !aligned(vel)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t n3 = (size_t)pc->n * pc->n * pc->n;
+    if (overlap(pos, 12 * n3, vel, 12 * n3) || overlap(psi, 3 * n3 * elem_size(pc->dtype), pos, 12 * n3) ||
+        overlap(psi, 3 * n3 * elem_size(pc->dtype), vel, 12 * n3))
+        return fail(GG_ERR_INVALID_ARG, "psi, pos and vel must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (pc->dtype == GG_F64) {
+        auto v = view<double>(pc);
+        for (int a = 0; a < 3; ++a) v.origin[a] = origin[a];
+        v.wrap = wrap_box;
+        e = gg::Ops<double>::zeldovich(v, static_cast<const double*>(psi), pos, vel, s);
+    } else {
+        auto v = view<float>(pc);
+        for (int a = 0; a < 3; ++a) v.origin[a] = origin[a];
+        v.wrap = wrap_box;
+        e = gg::Ops<float>::zeldovich(v, static_cast<const float*>(psi), pos, vel, s);
+    }
+    return e == hipSuccess ? GG_OK : fail_hip(e, "zeldovich launch");
 }
 
 gg_status gg_timing_enable(gg_plan* p, int on) {
@@ -704,3 +785,199 @@ gg_status gg_timing_read(gg_plan* p, double* ms, int npass, int* ncalls) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Zoom hierarchy (Sec. 2.3-2.4): one plan per level, run as one sequence of
+// launches on one stream, optionally captured once into a HIP graph and
+// replayed.
+// ---------------------------------------------------------------------------
+struct gg_zoom {
+    gg_zoom_desc d{};
+    gg_dtype dtype = GG_F32;
+    std::vector<gg_plan*> plans;
+    std::vector<double> box, cell;
+    std::vector<std::array<double, 3>> origin_box;  // level origin in the base box
+    size_t plan_work = 0;                           // max plan workspace
+    size_t tmp_bytes = 0;                           // 3 R of the largest parent
+    // captured graph and the arguments it was captured with
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+    uint64_t key_seed = 0;
+};
+
+namespace {
+
+void zoom_free(gg_zoom* z) {
+    if (!z) return;
+    if (z->exec) hipGraphExecDestroy(z->exec);
+    if (z->graph) hipGraphDestroy(z->graph);
+    for (gg_plan* p : z->plans) gg_plan_destroy(p);
+    delete z;
+}
+
+// n^2 bound of the top hat f(k r_s) = [k r_s < 1] on a box of side L
+int64_t zoom_cut(double box, double r_s) {
+    const double t = box / (2.0 * 3.14159265358979323846 * r_s);
+    return (int64_t)std::ceil(t * t);
+}
+
+}  // namespace
+
+gg_status gg_zoom_create(gg_zoom** out, const gg_zoom_desc* d, const gg_cosmo* cosmo, gg_dtype dtype) {
+    if (!out || !d || !cosmo) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zoom_create");
+    if (d->levels < 1 || d->levels > GG_ZOOM_MAX_LEVELS) return fail(GG_ERR_INVALID_ARG, "levels must be in [1, 8]");
+    if (!(d->box > 0) || !std::isfinite(d->box)) return fail(GG_ERR_INVALID_ARG, "box must be > 0");
+    int nl = 0, nh = 0;
+    gg::refine_sizes((int)d->variant, nl, nh);
+    if (nl == 0 || nh != 2 * nl) return fail(GG_ERR_INVALID_ARG, "zoom levels refine by two: variant HR, 4, LINEAR or SINE");
+    for (int l = 0; l < d->levels; ++l) {
+        if (!gg::supported_n(d->n[l])) return fail(GG_ERR_UNSUPPORTED_SIZE, "unsupported level size");
+        if (l > 0) {
+            const int span = d->n[l] / 2;
+            if (d->n[l] % (2 * nl) || span > d->n[l - 1])
+                return fail(GG_ERR_INVALID_ARG, "a level spans n/2 parent cells (a multiple of N_L, within the parent)");
+            for (int a = 0; a < 3; ++a) {
+                const int o = d->origin[l][a];
+                if (o < 0 || o >= d->n[l - 1]) return fail(GG_ERR_INVALID_ARG, "origin outside the parent lattice");
+                // levels below the first sit inside their parent's sub-box (no wrap)
+                if (l > 1 && o + span > d->n[l - 1])
+                    return fail(GG_ERR_INVALID_ARG, "a nested level must lie inside its parent sub-box");
+            }
+        }
+    }
+    gg_zoom* z = new (std::nothrow) gg_zoom;
+    if (!z) return fail(GG_ERR_OUT_OF_MEMORY, "zoom");
+    z->d = *d;
+    z->dtype = dtype;
+    const size_t es = elem_size(dtype);
+    double cell = d->box / d->n[0];
+    std::array<double, 3> org{0.0, 0.0, 0.0};
+    for (int l = 0; l < d->levels; ++l) {
+        if (l > 0) {
+            for (int a = 0; a < 3; ++a) org[a] = std::fmod(org[a] + d->origin[l][a] * cell, d->box);
+            cell *= 0.5;
+        }
+        const double box = d->n[l] * cell;
+        gg_grid g{d->n[l], box};
+        gg_plan* p = nullptr;
+        gg_status st = gg_plan_create(&p, &g, cosmo, dtype);
+        if (st != GG_OK) {
+            zoom_free(z);
+            return st;
+        }
+        p->nchunk = 1;  // one stream: the whole hierarchy can be captured as a graph
+        z->plans.push_back(p);
+        z->box.push_back(box);
+        z->cell.push_back(cell);
+        z->origin_box.push_back(org);
+        z->plan_work = std::max(z->plan_work, gg_workspace_bytes(p));
+        if (l + 1 < d->levels) z->tmp_bytes = std::max(z->tmp_bytes, 3 * es * (size_t)d->n[l] * d->n[l] * d->n[l]);
+    }
+    *out = z;
+    return GG_OK;
+}
+
+gg_status gg_zoom_destroy(gg_zoom* z) {
+    if (!z) return GG_OK;
+    if (!z->plans.empty()) hipSetDevice(z->plans[0]->device);
+    hipDeviceSynchronize();
+    zoom_free(z);
+    return GG_OK;
+}
+
+size_t gg_zoom_workspace_bytes(const gg_zoom* z) {
+    if (!z) return 0;
+    return (z->plan_work + 255) / 256 * 256 + z->tmp_bytes;
+}
+
+gg_status gg_zoom_query(const gg_zoom* z, int32_t level, double* box, double* cell, double origin[3]) {
+    if (!z || !box || !cell || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zoom_query");
+    if (level < 0 || level >= z->d.levels) return fail(GG_ERR_INVALID_ARG, "level out of range");
+    *box = z->box[level];
+    *cell = z->cell[level];
+    for (int a = 0; a < 3; ++a) origin[a] = z->origin_box[level][a];
+    return GG_OK;
+}
+
+namespace {
+
+gg_status zoom_sequence(gg_zoom* z, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
+                        float* const* vel, void* work, void* stream) {
+    const gg_zoom_desc& d = z->d;
+    char* wk = static_cast<char*>(work);
+    void* tmp = wk + (z->plan_work + 255) / 256 * 256;
+    const size_t es = elem_size(z->dtype);
+    gg_status st;
+#define GG_Z(expr) \
+    if ((st = (expr)) != GG_OK) return st;
+    GG_Z(gg_noise(z->plans[0], seed, 0u, w[0], stream))
+    GG_Z(gg_make_ic_from_noise(z->plans[0], w[0], 1.0, pos[0], vel[0], psi[0], work, stream))
+    for (int l = 1; l < d.levels; ++l) {
+        const int np = d.n[l - 1], n = d.n[l];
+        const double r_s = 2.0 * z->cell[l - 1];
+        GG_Z(gg_refine_noise_region(np, d.origin[l], n / 2, z->dtype, (gg_refine)d.variant, w[l - 1], seed, (uint32_t)l,
+                                    w[l], stream))
+        GG_Z(gg_make_displacements(z->plans[l], w[l], zoom_cut(z->box[l], r_s), 0, 0, psi[l], work, stream))
+        const size_t rp = es * (size_t)np * np * np;
+        for (int j = 0; j < 3; ++j)
+            GG_Z(gg_lowpass(z->plans[l - 1], static_cast<char*>(psi[l - 1]) + j * rp, zoom_cut(z->box[l - 1], r_s), 1,
+                            static_cast<char*>(tmp) + j * rp, work, stream))
+        GG_Z(gg_interpolate_add_at(np, 2, d.origin[l], n, z->dtype, tmp, psi[l], stream))
+        GG_Z(gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], stream))
+    }
+#undef GG_Z
+    return GG_OK;
+}
+
+}  // namespace
+
+gg_status gg_zoom_run(gg_zoom* z, uint64_t seed, void* const* w, void* const* psi, float* const* pos, float* const* vel,
+                      void* work, int32_t use_graph, void* stream) {
+    if (!z || !w || !psi || !pos || !vel || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zoom_run");
+    for (int l = 0; l < z->d.levels; ++l)
+        if (!w[l] || !psi[l] || !pos[l] || !vel[l]) return fail(GG_ERR_INVALID_ARG, "null level buffer");
+    if (!aligned(work)) return fail(GG_ERR_INVALID_ARG, "work must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!use_graph) return zoom_sequence(z, seed, w, psi, pos, vel, work, stream);
+    std::vector<const void*> key;
+    for (int l = 0; l < z->d.levels; ++l) {
+        key.push_back(w[l]);
+        key.push_back(psi[l]);
+        key.push_back(pos[l]);
+        key.push_back(vel[l]);
+    }
+    key.push_back(work);
+    key.push_back(stream);
+    if (!z->exec || key != z->key || seed != z->key_seed) {
+        if (z->exec) {
+            hipGraphExecDestroy(z->exec);
+            z->exec = nullptr;
+        }
+        if (z->graph) {
+            hipGraphDestroy(z->graph);
+            z->graph = nullptr;
+        }
+        if (s == nullptr) return fail(GG_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
+        const gg_status st = zoom_sequence(z, seed, w, psi, pos, vel, work, stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (st != GG_OK) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&z->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return fail_hip(e, "hipGraphInstantiate");
+        }
+        z->graph = g;
+        z->key = key;
+        z->key_seed = seed;
+    }
+    const hipError_t e = hipGraphLaunch(z->exec, s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "hipGraphLaunch");
+}

@@ -49,6 +49,11 @@ struct PlanView {
     int n2_lo;
     int n2_hi;
     int deconv;
+    // particle lattice q_j = origin[j] + (m_j + offset) cell, wrapped into
+    // [0, wrap): a zoom level's sub-box inside the base box (origin 0 and
+    // wrap = box for a full box)
+    double origin[3];
+    double wrap;
 };
 
 // 1 / sinc^2(pi s / N), the inverse of one axis of the cloud-in-cell window
@@ -297,10 +302,10 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
 // float rounding, L -> 0) and velocity a H f psi in the path's type.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void zel_point(T psi, int m, double cell, double offset, double box, T vfac, float& pos,
-                                          float& vel) {
+__device__ __forceinline__ void zel_point(T psi, int m, double origin, double cell, double offset, double box, T vfac,
+                                          float& pos, float& vel) {
 #pragma clang fp contract(off)
-    const double q = ((double)m + offset) * cell;
+    const double q = origin + ((double)m + offset) * cell;
     double x = q + (double)psi;
     if (x < 0.0) x = x + box;
     else if (x >= box) x = x - box;
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int mm = comp == 0 ? m0 : (comp == 1 ? m1 : 2 * m + e);
-                zel_point<T>(vals[e], mm, pv.cell, pv.offset, pv.box, (T)pv.vfac, p[e], u[e]);
+                zel_point<T>(vals[e], mm, pv.origin[comp], pv.cell, pv.offset, pv.wrap, (T)pv.vfac, p[e], u[e]);
             }
             if (za.pos) *reinterpret_cast<float4*>(za.pos + off) = make_float4(p[0], p[1], p[2], p[3]);
             if (za.vel) *reinterpret_cast<float4*>(za.vel + off) = make_float4(u[0], u[1], u[2], u[3]);
@@ -670,6 +675,27 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 }
 
 // ---------------------------------------------------------------------------
+// Eq. 5 window on a plain half spectrum (rows (k0, k1), k2 in [0, N/2]):
+// modes with n^2 >= n2_max are zeroed, the others divided by the CiC window
+// prod_j sinc^2(pi s_j / N) if deconv is set.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_window(cx<T>* __restrict__ spec, int n, int n2_max, int deconv) {
+    const int K = n / 2 + 1;
+    const uint64_t total = (uint64_t)n * n * K;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int k2 = (int)(i % K);
+        const uint64_t r = i / K;
+        const int k1 = (int)(r % n), k0 = (int)(r / n);
+        const int s0 = k0 <= n / 2 ? k0 : k0 - n, s1 = k1 <= n / 2 ? k1 : k1 - n;
+        const int n2 = s0 * s0 + s1 * s1 + k2 * k2;
+        T f = n2 < n2_max ? (T)1 : (T)0;
+        if (deconv && n2 < n2_max) f = cic_deconv<T>(s0, n) * cic_deconv<T>(s1, n) * cic_deconv<T>(k2, n);
+        spec[i] = cscale(spec[i], f);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Stand-alone Eq. (1)-(2) on a full half spectrum (k2 in [0, N/2]).
 // tau here carries the 1/N^3 of the fused path; scale = N^3 removes it.
 // ---------------------------------------------------------------------------
@@ -711,7 +737,7 @@ __global__ void k_zeldovich(const T* __restrict__ psi, float* __restrict__ pos, 
         if (comp == 0) m = (int)(cell / ((uint64_t)n * n));
         else if (comp == 1) m = (int)((cell / n) % n);
         else m = (int)(cell % n);
-        zel_point<T>(psi[idx], m, pv.cell, pv.offset, pv.box, (T)pv.vfac, pos[idx], vel[idx]);
+        zel_point<T>(psi[idx], m, pv.origin[comp], pv.cell, pv.offset, pv.wrap, (T)pv.vfac, pos[idx], vel[idx]);
     }
 }
 

@@ -62,10 +62,17 @@ struct Ops {
                                   hipStream_t s);
     // white-noise refinement (App. A), variant gg_refine value: parent
     // (n_parent)^3 -> child (n_parent / NL * NH)^3
-    static hipError_t refine(int variant, const T* parent, int n_parent, uint64_t seed, uint32_t stream_id, T* child,
-                             hipStream_t s);
-    // dst (3 fields of n_dst^3) += cloud-in-cell interpolation of src (3 fields of n_src^3)
-    static hipError_t cic_add(const T* src, int n_src, T* dst, int n_dst, hipStream_t s);
+    // the parent cells origin + [0, count) per axis (periodic in n_parent^3)
+    static hipError_t refine(int variant, const T* parent, int n_parent, const int origin[3], int count,
+                             uint64_t seed, uint32_t stream_id, T* child, hipStream_t s);
+    // dst (3 fields of n_dst^3) += cloud-in-cell interpolation of the periodic
+    // src (3 fields of n_src^3) at origin + m / ratio (src cells)
+    static hipError_t cic_add(const T* src, int n_src, int ratio, const int origin[3], T* dst, int n_dst,
+                              hipStream_t s);
+    // Eq. 5 on a real field: modes with n^2 >= n2_max dropped, optional CiC
+    // deconvolution; out (R) may equal field; work: two plain half spectra
+    static hipError_t lowpass(const PlanView<T>& pv, const T* field, int n2_max, int deconv, T* out, cx<T>* work,
+                              hipStream_t s);
     static hipError_t fused_forward(const PlanView<T>& pv, const T* w, uint64_t seed, float* pos, float* vel, T* psi,
                                     cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)

@@ -393,16 +393,18 @@ hipError_t Ops<T>::field_stats(const T* field, uint64_t count, double* out, doub
 }
 
 template <typename T>
-hipError_t Ops<T>::refine(int variant, const T* parent, int n_parent, uint64_t seed, uint32_t stream_id, T* child,
-                          hipStream_t s) {
+hipError_t Ops<T>::refine(int variant, const T* parent, int n_parent, const int origin[3], int count, uint64_t seed,
+                          uint32_t stream_id, T* child, hipStream_t s) {
     auto run = [&](auto vc) -> hipError_t {
         constexpr int VAR = decltype(vc)::value;
         constexpr int NL = RefineBasis<VAR>::NL;
-        if (n_parent < NL || n_parent % NL) return hipErrorInvalidValue;
-        const int P = n_parent / NL;
+        if (count < NL || count % NL || count > n_parent) return hipErrorInvalidValue;
+        for (int a = 0; a < 3; ++a)
+            if (origin[a] < 0 || origin[a] >= n_parent) return hipErrorInvalidValue;
+        const int P = count / NL;
         const uint64_t np = (uint64_t)P * P * P;
         k_refine<T, VAR><<<(unsigned)((np + kRefineThreads - 1) / kRefineThreads), kRefineThreads, 0, s>>>(
-            parent, P, seed, stream_id, child);
+            parent, n_parent, origin[0], origin[1], origin[2], P, seed, stream_id, child);
         return hipGetLastError();
     };
     switch (variant) {
@@ -416,11 +418,27 @@ hipError_t Ops<T>::refine(int variant, const T* parent, int n_parent, uint64_t s
 }
 
 template <typename T>
-hipError_t Ops<T>::cic_add(const T* src, int n_src, T* dst, int n_dst, hipStream_t s) {
-    if (n_src < 1 || n_dst < n_src || n_dst % n_src) return hipErrorInvalidValue;
+hipError_t Ops<T>::cic_add(const T* src, int n_src, int ratio, const int origin[3], T* dst, int n_dst,
+                           hipStream_t s) {
+    if (n_src < 1 || n_dst < 1 || ratio < 1) return hipErrorInvalidValue;
+    for (int a = 0; a < 3; ++a)
+        if (origin[a] < 0 || origin[a] >= n_src) return hipErrorInvalidValue;
     const uint64_t n3 = (uint64_t)n_dst * n_dst * n_dst;
-    k_cic_add<T><<<dim3(capped_grid(n3, 256), 3), 256, 0, s>>>(src, n_src, n_dst / n_src, dst);
+    k_cic_add<T><<<dim3(capped_grid(n3, 256), 3), 256, 0, s>>>(src, n_src, ratio, origin[0], origin[1], origin[2], dst,
+                                                               n_dst);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Ops<T>::lowpass(const PlanView<T>& pv, const T* field, int n2_max, int deconv, T* out, cx<T>* work,
+                           hipStream_t s) {
+    const int n = pv.n;
+    const size_t hsz = (size_t)n * n * (n / 2 + 1);
+    hipError_t e = fft_forward(pv, field, work, s);
+    if (e != hipSuccess) return e;
+    k_window<T><<<capped_grid(hsz, 256), 256, 0, s>>>(work, n, n2_max, deconv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return fft_inverse(pv, work, out, work + hsz, s);
 }
 
 template <typename T>

@@ -91,14 +91,16 @@ __device__ inline double refine_F(int i, int m) {
 }
 
 // One thread per patch, 64 patches (one wave) per work-group; P patches per
-// axis; parent (P NL)^3, child (P NH)^3.  The NH^3 coefficients of each patch
+// axis over the parent cells o + [0, P NL) (periodic in the npar^3 parent);
+// child (P NH)^3.  The NH^3 coefficients of each patch
 // sit in LDS ([coefficient][thread], conflict-free); the three 1D expansions
 // run in place there.
 constexpr int kRefineThreads = 64;
 
 template <typename T, int VAR>
-__global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__ parent, int P, uint64_t seed,
-                                                           uint32_t stream, T* __restrict__ child) {
+__global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__ parent, int npar, int o0, int o1,
+                                                           int o2, int P, uint64_t seed, uint32_t stream,
+                                                           T* __restrict__ child) {
     using B = RefineBasis<VAR>;
     constexpr int NL = B::NL, NH = B::NH, NC = NH * NH * NH;
     __shared__ double coef[NC * kRefineThreads];
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
     const uint64_t p = (uint64_t)blockIdx.x * kRefineThreads + t;
     if (p >= np) return;  // no barriers below: each thread works on its own LDS column
     const int p2 = (int)(p % P), p1 = (int)((p / P) % P), p0 = (int)(p / ((uint64_t)P * P));
-    const int64_t npar = (int64_t)P * NL, nch = (int64_t)P * NH;
+    const int64_t nch = (int64_t)P * NH;
     // new coefficients: every index combination with an index >= NL
 #pragma unroll 1
     for (int q = 0; q < NC; ++q) {
@@ -123,7 +125,8 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
         for (int n = 0; n < NL; ++n)
 #pragma unroll
             for (int l = 0; l < NL; ++l)
-                v[m][n][l] = (double)parent[(((int64_t)p0 * NL + m) * npar + (int64_t)p1 * NL + n) * npar + (int64_t)p2 * NL + l];
+                v[m][n][l] = (double)parent[((int64_t)((o0 + p0 * NL + m) % npar) * npar + (o1 + p1 * NL + n) % npar) * npar +
+                                            (o2 + p2 * NL + l) % npar];
 #pragma unroll
     for (int i = 0; i < NL; ++i)
 #pragma unroll
@@ -202,22 +205,23 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
         }
 }
 
-// dst (3 fields of nc^3) += trilinear interpolation of src (3 fields of np^3)
-// at the points m dx_c = (m / R) dx_p, R = nc / np (periodic).  The weights
-// are exact multiples of 1/R; products and sums in binary64, then rounded to T.
+// dst (3 fields of nd^3) += trilinear interpolation of the periodic src (3
+// fields of ns^3) at the points u = o + m / R (src cells), m < nd per axis.
+// The weights are exact multiples of 1/R; products and sums in binary64, then
+// rounded to T.
 template <typename T>
-__global__ void k_cic_add(const T* __restrict__ src, int np, int R, T* __restrict__ dst) {
-    const int nc = np * R;
-    const uint64_t n3c = (uint64_t)nc * nc * nc;
-    const uint64_t n3p = (uint64_t)np * np * np;
+__global__ void k_cic_add(const T* __restrict__ src, int ns, int R, int o0, int o1, int o2, T* __restrict__ dst,
+                          int nd) {
+    const uint64_t n3d = (uint64_t)nd * nd * nd;
+    const uint64_t n3s = (uint64_t)ns * ns * ns;
     const int comp = blockIdx.y;
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n3c; c += (uint64_t)gridDim.x * blockDim.x) {
-        const int z = (int)(c % nc), y = (int)((c / nc) % nc), x = (int)(c / ((uint64_t)nc * nc));
-        const int x0 = x / R, y0 = y / R, z0 = z / R;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n3d; c += (uint64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(c % nd), y = (int)((c / nd) % nd), x = (int)(c / ((uint64_t)nd * nd));
+        const int x0 = (o0 + x / R) % ns, y0 = (o1 + y / R) % ns, z0 = (o2 + z / R) % ns;
         const double tx = (double)(x % R) / R, ty = (double)(y % R) / R, tz = (double)(z % R) / R;
-        const int x1 = (x0 + 1) % np, y1 = (y0 + 1) % np, z1 = (z0 + 1) % np;
-        const T* s = src + comp * n3p;
-        auto at = [&](int i, int j, int k) { return (double)s[((uint64_t)i * np + j) * np + k]; };
+        const int x1 = (x0 + 1) % ns, y1 = (y0 + 1) % ns, z1 = (z0 + 1) % ns;
+        const T* s = src + comp * n3s;
+        auto at = [&](int i, int j, int k) { return (double)s[((uint64_t)i * ns + j) * ns + k]; };
         // interpolate along axis 0, then 1, then 2 (the oracle's order)
         const double a00 = at(x0, y0, z0) * (1.0 - tx) + at(x1, y0, z0) * tx;
         const double a10 = at(x0, y1, z0) * (1.0 - tx) + at(x1, y1, z0) * tx;
@@ -226,7 +230,7 @@ __global__ void k_cic_add(const T* __restrict__ src, int np, int R, T* __restric
         const double b0 = a00 * (1.0 - ty) + a10 * ty;
         const double b1 = a01 * (1.0 - ty) + a11 * ty;
         const double v = b0 * (1.0 - tz) + b1 * tz;
-        T* d = dst + comp * n3c + c;
+        T* d = dst + comp * n3d + c;
         *d = (T)((double)*d + v);
     }
 }

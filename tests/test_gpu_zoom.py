@@ -1,0 +1,176 @@
+"""GPU parity of the zoom hierarchy (nested uneven sub-boxes, Sec. 2.3-2.4)
+and its pieces against the FP64 oracle.
+
+Bars: FP64 fields 1e-12, FP32 2e-6 relative r.m.s. per level and component;
+refined noise within 1e-14 (FP64) / 1 ulp (FP32); float32 positions within
+one float32 ulp of the base box of the oracle's (periodic distance).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2511_10353_amd as gg
+from oracle import refine as oref
+from oracle import zoom as ozoom
+from tests import inputs
+from tests.gpu_util import oracle_cosmo, periodic_abs_diff, rel_rms, say, ulp_diff_f32
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 2e-6, "f64": 1e-12}
+NPDT = {"f32": np.float32, "f64": np.float64}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_refine_region_against_oracle(dtype):
+    n = 24
+    parent = inputs.real_field(n, 8, NPDT[dtype])
+    origin, count = (20, 3, 11), 12  # wraps around axis 0
+    got = gg.refine_noise_region(torch.from_numpy(parent).cuda(), origin, count, "4", seed=5, stream_id=2)
+    want = oref.refine(ozoom.periodic_slice(parent.astype(np.float64), origin, count), "4", 5, 2)
+    got = got.cpu().numpy()
+    if dtype == "f64":
+        assert np.abs(got - want).max() < 1e-14
+    else:
+        assert int(ulp_diff_f32(got, want.astype(np.float32)).max()) <= 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_interpolate_at_and_lowpass_against_oracle(dtype):
+    n, box = 32, 60.0
+    p = gg.Plan(n, box, gg.Cosmo(), dtype=dtype)
+    f = np.stack([inputs.real_field(n, 70 + j, NPDT[dtype]) for j in range(3)])
+    r_s = 2 * box / n
+    cut = gg.cutoff_n2(box, r_s)
+    low = torch.stack([p.lowpass(torch.from_numpy(f[j]).cuda(), cut) for j in range(3)])
+    want_low = np.stack([ozoom.lowpass(f[j].astype(np.float64), n, box, r_s) for j in range(3)])
+    err = rel_rms(low.cpu().numpy(), want_low)
+    say(f"[lowpass] {dtype} rel rms {err:.3e}")
+    assert err < TOL[dtype]
+    origin, nd = (25, 0, 9), 40
+    dst = torch.zeros((3, nd, nd, nd), dtype=p.real_dtype, device="cuda")
+    gg.interpolate_add_at(low, dst, origin, 2)
+    want = np.stack([ozoom.cic_at(low[j].cpu().numpy().astype(np.float64), origin, 2, nd) for j in range(3)])
+    got = dst.cpu().numpy()
+    if dtype == "f64":
+        assert np.abs(got - want).max() < 1e-14 * np.abs(want).max()
+    else:
+        assert int(ulp_diff_f32(got, want.astype(np.float32)).max()) <= 1
+
+
+def test_zeldovich_at_against_oracle():
+    n, cell, box0 = 32, 0.5, 40.0
+    p = gg.Plan(n, n * cell, gg.Cosmo(), dtype="f64")
+    psi = np.stack([0.3 * inputs.real_field(n, 90 + j) for j in range(3)])
+    origin = (30.0, 1.5, 0.0)
+    pos, vel = p.zeldovich_at(torch.from_numpy(psi).cuda(), origin, box0)
+    wpos, wvel = ozoom.particles(psi, n, cell, origin, box0, oracle_cosmo(p.cosmo))
+    assert np.array_equal(pos.cpu().numpy(), wpos)
+    assert np.array_equal(vel.cpu().numpy(), wvel)
+
+
+def _check_levels(z, levels_o, dtype, box0):
+    for l, (lv, lo) in enumerate(zip(z.levels, levels_o)):
+        assert abs(z.geometry[l]["cell"] - lo["cell"]) < 1e-15 * lo["cell"]
+        assert all(abs(a - b) < 1e-12 for a, b in zip(z.geometry[l]["origin"], lo["origin_box"]))
+        w = lv["w"].cpu().numpy()
+        if dtype == "f64":
+            assert np.abs(w - lo["w"]).max() < 1e-13
+        psi = lv["psi"].cpu().numpy()
+        for j in range(3):
+            err = rel_rms(psi[j], lo["psi"][j])
+            say(f"[zoom] level {l} n={lo['n']} {dtype} comp {j} rel rms {err:.3e}")
+            assert err < TOL[dtype]
+        d = periodic_abs_diff(lv["pos"].cpu().numpy(), lo["pos"], box0)
+        assert d.max() <= 2 * np.spacing(np.float32(box0))
+
+
+def _oracle_levels(z, n0, box0, sizes, origins, seed, dtype):
+    """The oracle hierarchy fed the noise each GPU level consumed (float32
+    rounding of the refined noise on the float path)."""
+    c = oracle_cosmo(gg.Cosmo())
+    if dtype == "f64":
+        return ozoom.hierarchy(n0, box0, sizes, origins, seed, c, workers=8)
+    # float path: rebuild level by level from the GPU's own noise fields
+    import oracle.pipeline as opipe
+    out = []
+    psi_prev = None
+    for l, lv in enumerate(z.levels):
+        geo = z.geometry[l]
+        n = lv["w"].shape[0]
+        w = lv["w"].cpu().numpy().astype(np.float64)
+        if l == 0:
+            psi = np.stack(opipe.displacement_fields(w, n, box0, c, workers=8))
+        else:
+            pn = z.levels[l - 1]["w"].shape[0]
+            psi = ozoom.level_displacements(w, n, geo["box"], psi_prev, pn, z.geometry[l - 1]["box"], origins[l - 1], c,
+                                            workers=8)
+        pos, vel = ozoom.particles(psi, n, geo["cell"], geo["origin"], box0, c)
+        out.append(dict(n=n, cell=geo["cell"], origin_box=geo["origin"], w=w, psi=psi, pos=pos, vel=vel))
+        psi_prev = psi
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_small_hierarchy_against_oracle(dtype):
+    n0, box0 = 64, 100.0
+    sizes = [96, 64]
+    origins = [(50, 3, 17), (30, 36, 26)]  # level 1 wraps around the base box
+    z = gg.Zoom(n0, box0, sizes, origins, dtype=dtype)
+    z.run(11)
+    torch.cuda.synchronize()
+    _check_levels(z, _oracle_levels(z, n0, box0, sizes, origins, 11, dtype), dtype, box0)
+    z.close()
+
+
+def test_zoom_hierarchy_256_192_160_96():
+    # base 256^3 (300 Mpc/h) + 192^3, 160^3, 96^3 at 2x, 4x, 8x, nested centres from PCG64 seed 42; FP32
+    n0, box0 = 256, 300.0
+    sizes = [192, 160, 96]
+    origins = ozoom.nested_origins(n0, sizes, seed=42)
+    say(f"[zoom] origins {origins}")
+    z = gg.Zoom(n0, box0, sizes, origins, dtype="f32")
+    z.run(42)
+    torch.cuda.synchronize()
+    _check_levels(z, _oracle_levels(z, n0, box0, sizes, origins, 42, "f32"), "f32", box0)
+    # the refined noise of each level against the oracle's refinement of the GPU parent noise (1 ulp)
+    for l in range(1, 4):
+        par = z.levels[l - 1]["w"].cpu().numpy().astype(np.float64)
+        want = oref.refine(ozoom.periodic_slice(par, origins[l - 1], sizes[l - 1] // 2), "4", 42, l)
+        assert int(ulp_diff_f32(z.levels[l]["w"].cpu().numpy(), want.astype(np.float32)).max()) <= 1
+    z.close()
+
+
+def test_zoom_graph_replays_match_eager():
+    n0, box0 = 64, 100.0
+    sizes, origins = [96, 64], [(50, 3, 17), (30, 36, 26)]
+    z = gg.Zoom(n0, box0, sizes, origins, dtype="f32")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        z.run(5)
+        eager = [{k: v.clone() for k, v in lv.items()} for lv in z.levels]
+        for rep in range(4):
+            for lv in z.levels:
+                for v in lv.values():
+                    v.fill_(float("nan"))  # eager work between replays
+            torch.cuda.synchronize()
+            z.run(5, use_graph=True)
+            torch.cuda.synchronize()
+            for lv, ev in zip(z.levels, eager):
+                for k in ev:
+                    assert torch.equal(lv[k], ev[k]), (rep, k)
+        # another seed is captured again
+        z.run(6, use_graph=True)
+        torch.cuda.synchronize()
+        other = z.levels[0]["w"].clone()
+        z.run(6)
+        torch.cuda.synchronize()
+        assert torch.equal(other, z.levels[0]["w"])
+    z.close()
+
+
+def test_zoom_rejects_bad_descriptions():
+    with pytest.raises(gg.GGError):
+        gg.Zoom(64, 100.0, [100], [(0, 0, 0)])  # unsupported size
+    with pytest.raises(gg.GGError):
+        gg.Zoom(64, 100.0, [96, 64], [(0, 0, 0), (80, 0, 0)])  # level 2 outside its parent
