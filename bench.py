@@ -69,11 +69,12 @@ def pass_bytes(n, elem):
             3 * spec + particles]      # P5: read A, B, C, write pos, vel
 
 
-def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42):
+def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42, autotune=True):
     plan = gg.Plan(n, box, gg.Cosmo(), dtype=dtype)
     pos = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
     vel = torch.empty_like(pos)
     work = plan.workspace()
+    tuning = plan.autotune(reps=3, pos=pos, vel=vel, work=work) if autotune else []
     for i in range(warmup):
         plan.make_ic(seed + i, pos, vel, work=work)
     torch.cuda.synchronize()
@@ -104,10 +105,51 @@ def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42):
         passes.append({"pass": name, "launches": launches, "ms": round(t, 4), "ms_per_launch": round(t_launch, 4),
                        "bytes_per_launch": int(b_launch), "GB/s": round(gbs, 1),
                        "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+    chosen = {"chunks": plan.info["chunks"], "p1_lines": plan.info["p1_lines"], "z_lines": plan.info["z_lines"]}
     del pos, vel, work, plan
     torch.cuda.empty_cache()
     return {"ms_per_step": ms, "wall_s": wall, "cells_per_s": n ** 3 / (ms * 1e-3), "passes": passes,
-            "bytes_per_step": sum(nbytes), "chunks": chunks}
+            "bytes_per_step": sum(nbytes), "chunks": chunks, "tuning": chosen,
+            "autotune": [dict(t, ms=round(t["ms"], 3)) for t in tuning]}
+
+
+def time_zoom(gg, torch, steps, seed=42):
+    """The nested zoom hierarchy: base 256^3 over 300 Mpc/h plus 192^3, 160^3,
+    96^3 levels at 2x, 4x, 8x (origins from PCG64 seed 42), FP32; one step =
+    every level's noise, displacements and particles; eager launches and one
+    replayed HIP graph."""
+    import numpy as np
+    n0, box0, sizes = 256, 300.0, [192, 160, 96]
+    rng = np.random.default_rng(42)
+    origins, parent = [], n0
+    for lev, n in enumerate(sizes, start=1):
+        if lev == 1:
+            o = tuple(int(v) for v in rng.integers(0, n0, 3))
+        else:
+            o = tuple(int(v) for v in rng.integers(parent // 4, parent - parent // 4 - n // 2 + 1, 3))
+        origins.append(o)
+        parent = n
+    z = gg.Zoom(n0, box0, sizes, origins, dtype="f32")
+    s = torch.cuda.Stream()
+    out = {"workload": "zoom: 256^3 / 300 Mpc/h + 192^3, 160^3, 96^3 at 2x, 4x, 8x, FP32", "origins": origins}
+    cells = sum(n ** 3 for n in [n0] + sizes)
+    with torch.cuda.stream(s):
+        for mode in ("eager", "graph"):
+            g = mode == "graph"
+            z.run(seed, use_graph=g)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            for _ in range(steps):
+                z.run(seed, use_graph=g)
+            b.record(s)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            out[mode] = {"ms_per_hierarchy": round(ms, 4), "cells_per_s": round(cells / (ms * 1e-3), 1)}
+    z.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_bytes(n, elem, log_amp):
@@ -197,6 +239,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-zoom", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 4 GiB streaming copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -212,10 +256,10 @@ def main():
         print(json.dumps(calibrate_copy(torch)), flush=True)
         return 0
     gg.lib()
-    f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup)
+    f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup, autotune=not args.no_autotune)
     f64 = None
     if not args.no_fp64:
-        f64 = time_path(gg, torch, args.n, args.box, "f64", args.fp64_steps, 1)
+        f64 = time_path(gg, torch, args.n, args.box, "f64", args.fp64_steps, 1, autotune=not args.no_autotune)
     # dominant kernel: the longest single launch (P1-P4 run as overlapping
     # chunks on two streams, P5 as one launch on its own)
     dom = max(f32["passes"], key=lambda p: p["ms_per_launch"])
@@ -249,8 +293,12 @@ def main():
     }
     if f64 is not None:
         out["fp64"] = {"value": round(f64["cells_per_s"], 1), "unit": "cells/s",
-                       "ms_per_step": round(f64["ms_per_step"], 4), "passes": f64["passes"],
+                       "ms_per_step": round(f64["ms_per_step"], 4), "passes": f64["passes"], "tuning": f64["tuning"],
                        "fp32_speedup": round(f64["ms_per_step"] / f32["ms_per_step"], 3)}
+    out["config"]["tuning"] = f32["tuning"]
+    out["autotune"] = f32["autotune"]
+    if not args.no_zoom:
+        out["zoom"] = time_zoom(gg, torch, max(args.steps // 2, 1))
     if not args.no_adjoint:
         out["adjoint"] = time_adjoint(gg, torch, args.n, args.box, "f32", max(args.steps // 2, 1), 1)
     if not args.no_cpu:

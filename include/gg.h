@@ -108,6 +108,8 @@ typedef struct {
     size_t spectrum_elems;   /* N N (N/2+1) complex values */
     size_t workspace_bytes;  /* = gg_workspace_bytes(plan) */
     int32_t chunks;          /* launches per pass of P1-P4 in gg_make_ic (pipelining) */
+    int32_t p1_lines;        /* lattice lines per work-group of the first pass */
+    int32_t z_lines;         /* lattice lines per work-group of the last (particle) pass */
 } gg_plan_info;
 
 typedef struct gg_plan gg_plan;
@@ -310,6 +312,27 @@ gg_status gg_zoom_query(const gg_zoom* zoom, int32_t level, double* box, double*
  * same (captured again otherwise).  Calls on one zoom must not overlap. */
 gg_status gg_zoom_run(gg_zoom* zoom, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
                       float* const* vel, void* work, int32_t use_graph, void* stream);
+
+/* Launch configuration of the fused path: chunks (pipelined launches per pass,
+ * 1 = none; 0 keeps the current value), lines per work-group of the first and
+ * of the last pass (0 = built-in; otherwise the full LDS row of lines, 16 for
+ * float / 8 for double, or half of it).  INVALID_ARG for a choice the lattice
+ * does not allow.  Not safe while the plan is in use. */
+gg_status gg_plan_set_tuning(gg_plan* plan, int32_t chunks, int32_t p1_lines, int32_t z_lines);
+
+/* Autotuner: times gg_make_ic (one warm-up, then reps calls, HIP events on
+ * `stream`) for every valid combination of chunks (1, 2, 4, 8) and the two
+ * line counts of the first and last passes, keeps the fastest in the plan,
+ * and reports each combination (up to `capacity` entries; *count = number
+ * timed).  pos, vel, work as for gg_make_ic (overwritten).  Synchronous. */
+typedef struct {
+    int32_t chunks;
+    int32_t p1_lines;
+    int32_t z_lines;
+    double ms;
+} gg_tune_entry;
+gg_status gg_plan_autotune(gg_plan* plan, float* pos, float* vel, void* work, int32_t reps, gg_tune_entry* results,
+                           int32_t capacity, int32_t* count, void* stream);
 
 /* Per-pass timing of gg_make_ic with HIP events recorded on the call's
  * stream.  Enable before the calls to time; gg_timing_read waits for the last

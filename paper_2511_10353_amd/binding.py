@@ -37,12 +37,18 @@ class _Cosmo(ctypes.Structure):
                 ("lattice_offset", ctypes.c_double)]
 
 
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_int32), ("p1_lines", ctypes.c_int32), ("z_lines", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("box", ctypes.c_double),
                 ("amplitude", ctypes.c_double), ("sigma8_integral", ctypes.c_double),
                 ("growth", ctypes.c_double), ("velocity_factor", ctypes.c_double),
                 ("real_elems", ctypes.c_size_t), ("spectrum_elems", ctypes.c_size_t),
-                ("workspace_bytes", ctypes.c_size_t), ("chunks", ctypes.c_int32)]
+                ("workspace_bytes", ctypes.c_size_t), ("chunks", ctypes.c_int32), ("p1_lines", ctypes.c_int32),
+                ("z_lines", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
@@ -93,6 +99,8 @@ _SIGS = {
     "gg_zoom_workspace_bytes": (ctypes.c_size_t, [_VP]),
     "gg_zoom_query": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "gg_zoom_run": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    "gg_plan_set_tuning": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "gg_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, ctypes.c_int32, _VP, _VP]),
     "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_timing_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -327,6 +335,31 @@ class Plan:
         o = (ctypes.c_double * 3)(*[float(v) for v in origin])
         _check(lib().gg_zeldovich_at(self._h, _ptr(psi), o, float(wrap_box), _ptr(pos), _ptr(vel), _stream()))
         return pos, vel
+
+    def _refresh_info(self):
+        info = _Info()
+        _check(lib().gg_plan_query(self._h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+
+    def set_tuning(self, chunks=0, p1_lines=0, z_lines=0):
+        """Launch configuration of gg_make_ic (0 = keep / built-in)."""
+        _check(lib().gg_plan_set_tuning(self._h, int(chunks), int(p1_lines), int(z_lines)))
+        self._refresh_info()
+
+    def autotune(self, reps=3, pos=None, vel=None, work=None):
+        """Time every valid (chunks, p1_lines, z_lines) for gg_make_ic, keep the
+        fastest; returns the list of timed configurations."""
+        pos = self._need(pos, (3,) + self._real_shape(), torch.float32, "pos")
+        vel = self._need(vel, (3,) + self._real_shape(), torch.float32, "vel")
+        if work is None:
+            work = self.workspace()
+        cap = 64
+        res = (_TuneEntry * cap)()
+        count = ctypes.c_int32()
+        _check(lib().gg_plan_autotune(self._h, _ptr(pos), _ptr(vel), _ptr(work), int(reps), res, cap,
+                                      ctypes.byref(count), _stream()))
+        self._refresh_info()
+        return [dict(chunks=r.chunks, p1_lines=r.p1_lines, z_lines=r.z_lines, ms=r.ms) for r in res[:count.value]]
 
     def timing_enable(self, on=True):
         _check(lib().gg_timing_enable(self._h, 1 if on else 0))

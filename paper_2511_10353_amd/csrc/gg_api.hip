@@ -52,6 +52,9 @@ struct gg_plan {
     int64_t ntau = 0;
     void* tauseg = nullptr;  // float plans: kTauSeg float4 (piecewise-cubic tau)
     double amplitude = 0, sigma_int = 0, growth = 0, vfac = 0, cell = 0;
+    // tile choices of the fused path (0 = built-in; set by gg_plan_set_tuning
+    // or gg_plan_autotune)
+    int p1_lines = 0, z_lines = 0;
     // pipelined launch of the fused path: auxiliary stream, dependency events
     int nchunk = 1;
     hipStream_t aux = nullptr;
@@ -259,7 +262,7 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
                 nc = want;
         }
         p->nchunk = nc;
-        if (nc > 1) {
+        if (p->n >= 256) {  // pipelining possible: stream and events for any chunk count
             if ((e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking)) != hipSuccess) {
                 st = fail_hip(e, "hipStreamCreate (auxiliary)");
                 break;
@@ -320,6 +323,13 @@ gg_status gg_plan_query(const gg_plan* p, gg_plan_info* info) {
     info->spectrum_elems = (size_t)p->n * p->n * (p->n / 2 + 1);
     info->workspace_bytes = gg_workspace_bytes(p);
     info->chunks = p->nchunk;
+    {
+        int full = 0, half = 0, p1d = 0, zd = 0;
+        if (p->dtype == GG_F64) gg::Ops<double>::tile_options(p->n, full, half, p1d, zd);
+        else gg::Ops<float>::tile_options(p->n, full, half, p1d, zd);
+        info->p1_lines = p->p1_lines ? p->p1_lines : p1d;
+        info->z_lines = p->z_lines ? p->z_lines : zd;
+    }
     return GG_OK;
 }
 
@@ -429,6 +439,8 @@ gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, v
     x.b = p->aux;
     x.sync = p->sync.empty() ? nullptr : p->sync.data();
     x.nchunk = p->nchunk;
+    x.p1_lines = p->p1_lines;
+    x.z_lines = p->z_lines;
     if (p->timing && p->recorded < kTimingSlots) {
         x.tev = &p->events[(size_t)p->recorded * 2 * kLaunchesMax];
         p->recorded++;
@@ -467,6 +479,8 @@ gg_status gg_make_ic_from_noise(const gg_plan* pc, const void* w, double amp_sca
     x.b = p->aux;
     x.sync = p->sync.empty() ? nullptr : p->sync.data();
     x.nchunk = p->nchunk;
+    x.p1_lines = p->p1_lines;
+    x.z_lines = p->z_lines;
     hipError_t e;
     if (p->dtype == GG_F64) {
         auto v = view<double>(p);
@@ -650,6 +664,8 @@ gg_status gg_make_displacements(const gg_plan* pc, const void* w, int64_t n2_min
     x.b = p->aux;
     x.sync = p->sync.empty() ? nullptr : p->sync.data();
     x.nchunk = p->nchunk;
+    x.p1_lines = p->p1_lines;
+    x.z_lines = p->z_lines;
     hipError_t e;
     if (p->dtype == GG_F64) {
         auto v = view<double>(p);
@@ -745,6 +761,98 @@ gg_status gg_zeldovich_at(const gg_plan* pc, const void* psi, const double origi
         e = gg::Ops<float>::zeldovich(v, static_cast<const float*>(psi), pos, vel, s);
     }
     return e == hipSuccess ? GG_OK : fail_hip(e, "zeldovich launch");
+}
+
+namespace {
+
+bool chunks_valid(const gg_plan* p, int c) {
+    const int cblocks = (p->n / 2) / (p->dtype == GG_F64 ? gg::Tile<double>::L : gg::Tile<float>::L);
+    return c == 1 || (c >= 1 && c <= kMaxChunks && p->n >= 256 && p->aux && (p->n / 8) % c == 0 && cblocks % c == 0);
+}
+
+bool lines_valid(const gg_plan* p, int l) {
+    if (l == 0) return true;
+    int full = 0, half = 0, p1d = 0, zd = 0;
+    if (p->dtype == GG_F64) gg::Ops<double>::tile_options(p->n, full, half, p1d, zd);
+    else gg::Ops<float>::tile_options(p->n, full, half, p1d, zd);
+    return l == full || l == half;
+}
+
+}  // namespace
+
+gg_status gg_plan_set_tuning(gg_plan* p, int32_t chunks, int32_t p1_lines, int32_t z_lines) {
+    if (!p) return fail(GG_ERR_INVALID_ARG, "null plan");
+    if (chunks != 0 && !chunks_valid(p, chunks)) return fail(GG_ERR_INVALID_ARG, "chunk count not valid for this lattice");
+    if (!lines_valid(p, p1_lines) || !lines_valid(p, z_lines))
+        return fail(GG_ERR_INVALID_ARG, "lines must be 0 or the full or half LDS row of lines");
+    if (chunks != 0) p->nchunk = chunks;
+    p->p1_lines = p1_lines;
+    p->z_lines = z_lines;
+    return GG_OK;
+}
+
+gg_status gg_plan_autotune(gg_plan* p, float* pos, float* vel, void* work, int32_t reps, gg_tune_entry* results,
+                           int32_t capacity, int32_t* count, void* stream) {
+    if (!p || !pos || !vel || !work || !count) return fail(GG_ERR_INVALID_ARG, "null argument to gg_plan_autotune");
+    if (reps < 1 || reps > 100) return fail(GG_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    if (p->timing) return fail(GG_ERR_INVALID_ARG, "disable timing before autotuning");
+    int full = 0, half = 0, p1d = 0, zd = 0;
+    if (p->dtype == GG_F64) gg::Ops<double>::tile_options(p->n, full, half, p1d, zd);
+    else gg::Ops<float>::tile_options(p->n, full, half, p1d, zd);
+    std::vector<int> chunk_set, lines_set{full};
+    if (half != full) lines_set.push_back(half);
+    for (int c = 1; c <= kMaxChunks; c *= 2)
+        if (chunks_valid(p, c)) chunk_set.push_back(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) {
+        if (t0) hipEventDestroy(t0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    const int keep_c = p->nchunk, keep_1 = p->p1_lines, keep_z = p->z_lines;
+    double best = 1e300;
+    int bc = keep_c, b1 = keep_1, bz = keep_z;
+    int n = 0;
+    gg_status st = GG_OK;
+    for (int c : chunk_set)
+        for (int l1 : lines_set)
+            for (int lz : lines_set) {
+                p->nchunk = c;
+                p->p1_lines = l1;
+                p->z_lines = lz;
+                st = gg_make_ic(p, 0, pos, vel, nullptr, work, stream);  // warm-up
+                if (st != GG_OK) break;
+                if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+                for (int r = 0; r < reps && st == GG_OK; ++r) st = gg_make_ic(p, (uint64_t)r + 1, pos, vel, nullptr, work, stream);
+                if (st != GG_OK) break;
+                if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess) break;
+                float ms = 0.f;
+                if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+                const double per = (double)ms / reps;
+                if (results && n < capacity) results[n] = gg_tune_entry{c, l1, lz, per};
+                ++n;
+                if (per < best) {
+                    best = per;
+                    bc = c;
+                    b1 = l1;
+                    bz = lz;
+                }
+            }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (st != GG_OK || e != hipSuccess) {
+        p->nchunk = keep_c;
+        p->p1_lines = keep_1;
+        p->z_lines = keep_z;
+        return st != GG_OK ? st : fail_hip(e, "autotune timing");
+    }
+    p->nchunk = bc;
+    p->p1_lines = b1;
+    p->z_lines = bz;
+    *count = n;
+    return GG_OK;
 }
 
 gg_status gg_timing_enable(gg_plan* p, int on) {

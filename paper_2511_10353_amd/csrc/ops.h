@@ -31,6 +31,11 @@ struct ExecCtx {
     hipEvent_t* sync = nullptr;
     int nchunk = 1;
     hipEvent_t* tev = nullptr;
+    // lines per work-group of the first pass and of the last (particle) pass;
+    // 0 = the built-in choice.  Each accepts the type's full LDS row of lines
+    // (16 float, 8 double) or half of it.
+    int p1_lines = 0;
+    int z_lines = 0;
 };
 
 template <typename T>
@@ -77,6 +82,9 @@ struct Ops {
                                     cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)
     static int max_chunks(int n);
+    // the tile choices of ExecCtx for lattice n: full and half line counts of
+    // the axis-2 passes, and the built-in choices of the first and last pass
+    static void tile_options(int n, int& full, int& half, int& p1_default, int& z_default);
     // exact table tau[ntau]; for float plans also the piecewise-cubic
     // segments (kTauSeg float4) the fused passes evaluate
     static hipError_t tau_table(T* tau, int64_t ntau, float4* tauseg, int n, double box, double amp_growth2,

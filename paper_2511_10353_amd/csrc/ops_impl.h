@@ -55,6 +55,18 @@ struct P1Lines {
     static constexpr int L = fit >= ZLines<T, N>::L ? ZLines<T, N>::L : (fit >= 1 ? fit : 1);
 };
 
+// Runs f with the compile-time line count of an axis-2 pass chosen at run
+// time: `want` (0 = dflt) must be the full or the half tile.
+template <typename T, int N, typename F>
+hipError_t with_lines(int want, int dflt, F&& f) {
+    constexpr int LF = ZLines<T, N>::L;
+    constexpr int LH = LF / 2 >= 1 ? LF / 2 : 1;
+    const int l = want ? want : dflt;
+    if (l == LF) return f(std::integral_constant<int, LF>{});
+    if (l == LH) return f(std::integral_constant<int, LH>{});
+    return hipErrorInvalidValue;
+}
+
 inline unsigned capped_grid(uint64_t work, unsigned block) {
     uint64_t g = (work + block - 1) / block;
     const uint64_t cap = 256ull * 64ull;
@@ -154,6 +166,19 @@ hipError_t Ops<T>::zeldovich(const PlanView<T>& pv, const T* psi, float* pos, fl
 }
 
 template <typename T>
+void Ops<T>::tile_options(int n, int& full, int& half, int& p1_default, int& z_default) {
+    full = half = p1_default = z_default = 0;
+    dispatch_n(n, [&](auto nc) -> hipError_t {
+        constexpr int N = decltype(nc)::value;
+        full = ZLines<T, N>::L;
+        half = full / 2 >= 1 ? full / 2 : 1;
+        p1_default = P1Lines<T, N>::L;
+        z_default = ZLines<T, N>::L;
+        return hipSuccess;
+    });
+}
+
+template <typename T>
 int Ops<T>::max_chunks(int n) {
     // axis-0 slabs of whole 8-row groups and k2 chunks of whole column blocks;
     // measured best at 1024^3: 4 chunks (float), 2 (double)
@@ -213,19 +238,21 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
         for (int s = 0; s < NC; ++s) {
             launch = s;
             const uint64_t row0 = (uint64_t)s * xh * 8 * N;
-            constexpr int L1 = P1Lines<T, N>::L;
-            const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / L1);
             GG_TRY(mark(sa, 0))
-            if (w) {
-                const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
-                k_zfwd<T, N, ZSRC_REAL, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0, 0u,
-                                                                                                  row0);
-            } else {
-                const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
-                k_zfwd<T, N, ZSRC_NOISE, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, seed,
-                                                                                                   0u, row0);
-            }
-            GG_TRY(hipGetLastError())
+            GG_TRY((with_lines<T, N>(x.p1_lines, P1Lines<T, N>::L, [&](auto lc) -> hipError_t {
+                constexpr int L1 = decltype(lc)::value;
+                const unsigned blocks = (unsigned)((uint64_t)xh * 8 * N / L1);
+                if (w) {
+                    const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+                    k_zfwd<T, N, ZSRC_REAL, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0,
+                                                                                                      0u, row0);
+                } else {
+                    const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+                    k_zfwd<T, N, ZSRC_NOISE, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw,
+                                                                                                       seed, 0u, row0);
+                }
+                return hipGetLastError();
+            })))
             GG_TRY(mark(sa, 1))
             if (NC > 1) {
                 GG_TRY(hipEventRecord(x.sync[1 + s], sa))
@@ -261,9 +288,12 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
         }
         launch = 4 * NC;
         GG_TRY(mark(sa, 0))
-        k_zinv<T, N, 1, true, LZ><<<dim3(N * N / LZ, 3), LZ * PlanInfo<M>::TPL, 0, sa>>>(b1, b0, b2, M, nullptr, (T)1,
-                                                                                        pv, ZelArgs{pos, vel, psi});
-        GG_TRY(hipGetLastError())
+        GG_TRY((with_lines<T, N>(x.z_lines, LZ, [&](auto lc) -> hipError_t {
+            constexpr int L5 = decltype(lc)::value;
+            k_zinv<T, N, 1, true, L5><<<dim3(N * N / L5, 3), L5 * PlanInfo<M>::TPL, 0, sa>>>(
+                b1, b0, b2, M, nullptr, (T)1, pv, ZelArgs{pos, vel, psi});
+            return hipGetLastError();
+        })))
         GG_TRY(mark(sa, 1))
 #undef GG_TRY
         return hipSuccess;

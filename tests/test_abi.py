@@ -53,6 +53,9 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(gg_cosmo, amp), offsetof(gg_cosmo, lattice_offset), sizeof(gg_plan_info));
   printf("%zu %zu %zu %zu\n", offsetof(gg_plan_info, box), offsetof(gg_plan_info, real_elems),
          offsetof(gg_plan_info, workspace_bytes), offsetof(gg_plan_info, chunks));
+  printf("%zu %zu\n", offsetof(gg_plan_info, p1_lines), offsetof(gg_plan_info, z_lines));
+  printf("%zu %zu %zu\n", sizeof(gg_tune_entry), offsetof(gg_tune_entry, ms), sizeof(gg_zoom_desc));
+  printf("%zu %zu %zu\n", offsetof(gg_zoom_desc, origin), offsetof(gg_zoom_desc, box), offsetof(gg_zoom_desc, variant));
   return 0;
 }
 ''')
@@ -62,7 +65,9 @@ int main(void) {
     want = [ctypes.sizeof(binding._Grid), binding._Grid.box.offset, ctypes.sizeof(binding._Cosmo),
             binding._Cosmo.amp.offset, binding._Cosmo.lattice_offset.offset, ctypes.sizeof(binding._Info),
             binding._Info.box.offset, binding._Info.real_elems.offset, binding._Info.workspace_bytes.offset,
-            binding._Info.chunks.offset]
+            binding._Info.chunks.offset, binding._Info.p1_lines.offset, binding._Info.z_lines.offset,
+            ctypes.sizeof(binding._TuneEntry), binding._TuneEntry.ms.offset, ctypes.sizeof(binding._ZoomDesc),
+            binding._ZoomDesc.origin.offset, binding._ZoomDesc.box.offset, binding._ZoomDesc.variant.offset]
     assert got == want
 
 

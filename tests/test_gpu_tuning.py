@@ -1,0 +1,55 @@
+"""Launch-configuration choices of the fused path (chunks, tile lines of the
+first and last passes) and the autotuner: every valid choice gives the same
+bits, and the autotuner keeps one of the timed choices."""
+import pytest
+import torch
+
+import paper_2511_10353_amd as gg
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_every_configuration_gives_the_same_bits(dtype):
+    n, box = 256, 500.0
+    p = gg.Plan(n, box, gg.Cosmo(), dtype=dtype)
+    p.set_tuning(chunks=1)
+    ref = p.make_ic(3, want_psi=True)
+    torch.cuda.synchronize()
+    full = 16 if dtype == "f32" else 8
+    for chunks in (1, 2, 4, 8):
+        for l1 in (full, full // 2):
+            for lz in (full, full // 2):
+                p.set_tuning(chunks, l1, lz)
+                assert (p.info["chunks"], p.info["p1_lines"], p.info["z_lines"]) == (chunks, l1, lz)
+                out = p.make_ic(3, want_psi=True)
+                torch.cuda.synchronize()
+                for a, b in zip(out, ref):
+                    assert torch.equal(a, b), (chunks, l1, lz)
+
+
+def test_autotune_keeps_a_timed_configuration():
+    n, box = 256, 500.0
+    p = gg.Plan(n, box, gg.Cosmo(), dtype="f32")
+    table = p.autotune(reps=2)
+    say("[tune] " + ", ".join(f"{t['chunks']}/{t['p1_lines']}/{t['z_lines']}: {t['ms']:.3f} ms" for t in table))
+    assert len(table) == 4 * 2 * 2
+    best = min(table, key=lambda t: t["ms"])
+    assert (p.info["chunks"], p.info["p1_lines"], p.info["z_lines"]) == (best["chunks"], best["p1_lines"],
+                                                                         best["z_lines"])
+    a = p.make_ic(9)
+    p.set_tuning(1, 16, 16)
+    b = p.make_ic(9)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_invalid_tuning_rejected():
+    p = gg.Plan(64, 100.0, gg.Cosmo(), dtype="f32")
+    with pytest.raises(gg.GGError):
+        p.set_tuning(chunks=2)  # no pipelining below 256^3
+    with pytest.raises(gg.GGError):
+        p.set_tuning(p1_lines=12)
+    p.set_tuning(0, 8, 8)
+    assert p.info["p1_lines"] == 8 and p.info["z_lines"] == 8
