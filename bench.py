@@ -36,15 +36,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(pass_name):
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of a pass, from the
-    committed rocprofv3 summary, or None if the kernels changed since."""
+def stored_traffic(pass_name, tuning):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes of a pass over the whole lattice
+    (counters taken unchunked), from the committed rocprofv3 summary, or None
+    if the kernels changed since or the counters were taken with other tile
+    widths (the chunk count only splits a pass into launches)."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
     if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"tuning: chunks=(\d+) p1_lines=(\d+) z_lines=(\d+)", text)
+    if not m or (int(m.group(2)), int(m.group(3))) != (tuning["p1_lines"], tuning["z_lines"]):
         return None
     for line in text.splitlines():
         cols = [c.strip() for c in line.strip().strip("|").split("|")]
@@ -69,12 +74,16 @@ def pass_bytes(n, elem):
             3 * spec + particles]      # P5: read A, B, C, write pos, vel
 
 
-def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42, autotune=True):
+def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42, autotune=True, fixed=None):
     plan = gg.Plan(n, box, gg.Cosmo(), dtype=dtype)
     pos = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
     vel = torch.empty_like(pos)
     work = plan.workspace()
-    tuning = plan.autotune(reps=3, pos=pos, vel=vel, work=work) if autotune else []
+    tuning = []
+    if fixed is not None:
+        plan.set_tuning(*fixed)
+    elif autotune:
+        tuning = plan.autotune(reps=3, pos=pos, vel=vel, work=work)
     for i in range(warmup):
         plan.make_ic(seed + i, pos, vel, work=work)
     torch.cuda.synchronize()
@@ -241,6 +250,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-zoom", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None, metavar="CHUNKS,P1_LINES,Z_LINES",
+                    help="fixed launch configuration of the FP32 path instead of the autotuner "
+                         "(the FP64 path then keeps its built-in one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 4 GiB streaming copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -256,14 +268,17 @@ def main():
         print(json.dumps(calibrate_copy(torch)), flush=True)
         return 0
     gg.lib()
-    f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup, autotune=not args.no_autotune)
+    fixed = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup, autotune=not args.no_autotune,
+                    fixed=fixed)
     f64 = None
     if not args.no_fp64:
-        f64 = time_path(gg, torch, args.n, args.box, "f64", args.fp64_steps, 1, autotune=not args.no_autotune)
+        f64 = time_path(gg, torch, args.n, args.box, "f64", args.fp64_steps, 1,
+                        autotune=not (args.no_autotune or args.tuning))
     # dominant kernel: the longest single launch (P1-P4 run as overlapping
     # chunks on two streams, P5 as one launch on its own)
     dom = max(f32["passes"], key=lambda p: p["ms_per_launch"])
-    traffic = stored_traffic(dom["pass"]) if (args.n == 1024 and f32["chunks"] >= 1) else None
+    traffic = stored_traffic(dom["pass"], f32["tuning"]) if args.n == 1024 else None
     if traffic is not None:
         traffic = traffic / dom["launches"] if dom["launches"] > 1 else traffic
     roofline = {"bound": "hbm", "kernel": dom["pass"], "achieved": dom["GB/s"], "peak": HBM_PEAK_GBS,

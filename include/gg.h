@@ -322,8 +322,10 @@ gg_status gg_plan_set_tuning(gg_plan* plan, int32_t chunks, int32_t p1_lines, in
 
 /* Autotuner: times gg_make_ic (one warm-up, then reps calls, HIP events on
  * `stream`) for every valid combination of chunks (1, 2, 4, 8) and the two
- * line counts of the first and last passes, keeps the fastest in the plan,
- * and reports each combination (up to `capacity` entries; *count = number
+ * line counts of the first and last passes (in that order: fewer chunks and
+ * full tiles first), keeps the fastest in the plan -- a later combination
+ * replaces the best so far only when faster by more than 0.5 %, so that
+ * timing noise does not flip near-ties -- and reports each combination (up to `capacity` entries; *count = number
  * timed).  pos, vel, work as for gg_make_ic (overwritten).  Synchronous. */
 typedef struct {
     int32_t chunks;

@@ -791,6 +791,9 @@ gg_status gg_plan_set_tuning(gg_plan* p, int32_t chunks, int32_t p1_lines, int32
     return GG_OK;
 }
 
+// relative speed-up a later autotuner candidate needs to replace the best so far
+constexpr double kTuneMargin = 0.005;
+
 gg_status gg_plan_autotune(gg_plan* p, float* pos, float* vel, void* work, int32_t reps, gg_tune_entry* results,
                            int32_t capacity, int32_t* count, void* stream) {
     if (!p || !pos || !vel || !work || !count) return fail(GG_ERR_INVALID_ARG, "null argument to gg_plan_autotune");
@@ -833,7 +836,10 @@ gg_status gg_plan_autotune(gg_plan* p, float* pos, float* vel, void* work, int32
                 const double per = (double)ms / reps;
                 if (results && n < capacity) results[n] = gg_tune_entry{c, l1, lz, per};
                 ++n;
-                if (per < best) {
+                // a later configuration (more chunks, narrower tiles) must win by
+                // more than the timing noise, so that near-ties keep the simpler
+                // one and repeated tuning settles on the same choice
+                if (per < best * (1.0 - kTuneMargin)) {
                     best = per;
                     bc = c;
                     b1 = l1;

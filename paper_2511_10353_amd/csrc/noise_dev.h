@@ -136,23 +136,25 @@ __device__ __forceinline__ double gaussian_cell(uint64_t c, uint64_t seed, uint3
     return gaussian_words(w.x, w.y);
 }
 
-// The same deviate to about 2^-46 relative, for the float path: fused
-// multiply-adds, the atanh series to t^16 and the trigonometric series to
-// x^14 / x^15 (truncation below 2^-49 on the reduced ranges), reciprocal
-// and square root by hardware estimates refined with Newton steps.  Every
-// input it shares with gaussian_words (u1, m, e, x) is formed by the same
-// exact operations.
+// The same deviate to about 2^-46 relative, for the float path: the
+// exponent split by frexp, the atanh series to t^16 with a reciprocal
+// estimate refined by one Newton step, the square root by a reciprocal
+// square root estimate and one Goldschmidt step, and cos(2 pi u2) as
+// +-sin(2 pi n 2^-32) with n in [0, 2^30] (cos(alpha) = sin(pi/2 - alpha)
+// taken on the integer angle, so one odd Taylor series to x^19 covers every
+// quadrant; truncation below 2^-51 on [0, pi/2]).  The hardware estimates
+// are good to about 2^-24, so each refinement leaves about 2^-47.  u1, m and
+// e are the same exact values the defining sequence forms; r = -0 when
+// -2 ln u1 = 0, as sqrt(-0) gives there.
 __device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1) {
-    const double u1 = (double)((uint64_t)w0 + 1ull) * kTwoM32;
-    const uint64_t bits = (uint64_t)__double_as_longlong(u1);
-    int e = (int)((bits >> 52) & 0x7FF) - 1022;
-    const double f = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FE0000000000000ull));
+    const double u1 = fma((double)w0, kTwoM32, kTwoM32);  // (w0 + 1) 2^-32, exact
+    const double f = __builtin_amdgcn_frexp_mant(u1);     // u1 = f 2^e, f in [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(u1);
     const bool low = f < kSqrtHalfD;
     const double m = low ? f * 2.0 : f;
     e -= low ? 1 : 0;
     const double den = m + 1.0;
     double rc = __builtin_amdgcn_rcp(den);
-    rc = fma(rc, fma(-den, rc, 1.0), rc);
     rc = fma(rc, fma(-den, rc, 1.0), rc);
     const double t = (m - 1.0) * rc;
     const double s = t * t;
@@ -160,44 +162,38 @@ __device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1) 
 #pragma unroll
     for (int k = 7; k >= 0; --k) p = fma(p, s, atanh_coeff(k));
     const double a = fma((double)e, -2.0 * kLn2, -4.0 * (t * p));  // -2 ln u1 >= 0
-    // sqrt(a): reciprocal square root estimate, then Goldschmidt steps
     const double y = __builtin_amdgcn_rsq(a);
-    double g = a * y, h = 0.5 * y;
-    const double rr = fma(-g, h, 0.5);
-    g = fma(g, rr, g);
-    h = fma(h, rr, h);
-    g = fma(fma(-g, g, a), h, g);
-    const double r = a > 0.0 ? g : 0.0;
+    const double g0 = a * y, h0 = 0.5 * y;
+    const double rr = fma(-g0, h0, 0.5);
+    const double r = a > 0.0 ? fma(g0, rr, g0) : -0.0;
     const uint32_t q = w1 >> 30;
     const uint32_t rho = w1 & 0x3FFFFFFFu;
-    const bool direct = rho < (1u << 29);
-    const uint32_t n = direct ? rho : (1u << 30) - rho;
-    const double x = ((double)n * kTwoM32) * kTwoPi;
+    const uint32_t n = (q & 1u) ? rho : (1u << 30) - rho;
+    const double x = (double)n * (kTwoPi * kTwoM32);
     const double z = x * x;
-    double pc = cos_coeff(7), ps = sin_coeff(7);
+    double ps = sin_coeff(9);
 #pragma unroll
-    for (int k = 6; k >= 0; --k) {
-        pc = fma(pc, z, cos_coeff(k));
-        ps = fma(ps, z, sin_coeff(k));
-    }
-    const bool use_cos = ((q & 1u) == 0u) == direct;
-    const double v = use_cos ? pc : x * ps;
+    for (int k = 8; k >= 0; --k) ps = fma(ps, z, sin_coeff(k));
+    const double v = x * ps;
     return r * ((q == 1u || q == 2u) ? -v : v);
 }
 
 // Cell c's deviate in the path's type: binary64 as defined above, or that
-// value rounded once to float.  The float case rounds the fast evaluation
-// when the whole interval g +- 2^-42 |g| rounds to one float (rounding is
-// monotonic, so the exact deviate, within 2^-46 |g| of g, rounds there too)
-// and evaluates the defining sequence otherwise (about one cell in 10^5).
+// value rounded once to float.  The float case rounds the fast evaluation g
+// when every value within 2^-42 |g| of it rounds to the same float, and
+// evaluates the defining sequence otherwise (about one cell in 10^5); the
+// exact deviate lies within 2^-46 |g| of g.  The test works on the bits of
+// g: a float rounding boundary of a normal double lies where its 29 low
+// mantissa bits read 2^28, and 2^-42 |g| is below 2^11 units in the last
+// place of g, so g is safe when those bits are more than 2^11 from 2^28
+// (|g| > 2^-46 or g = 0 always, so float subnormals do not arise).
 template <typename T>
 __device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t stream) {
     const u32x4 w = cell_words(c, seed, stream);
     if constexpr (std::is_same_v<T, float>) {
         const double g = gaussian_words_fast(w.x, w.y);
-        const double tol = fabs(g) * 0x1p-42;
-        const float fg = (float)g;
-        if (__builtin_expect((float)(g - tol) == fg && (float)(g + tol) == fg, 1)) return fg;
+        const uint32_t lo29 = (uint32_t)__double_as_longlong(g) & 0x1FFFFFFFu;
+        if (__builtin_expect(lo29 - 0x10000000u + 2048u > 4096u, 1)) return (float)g;
         return (float)gaussian_words(w.x, w.y);
     } else {
         return gaussian_words(w.x, w.y);

@@ -1,6 +1,6 @@
 """Launch-configuration choices of the fused path (chunks, tile lines of the
 first and last passes) and the autotuner: every valid choice gives the same
-bits, and the autotuner keeps one of the timed choices."""
+bits, and the autotuner keeps the timed choice its margin rule selects."""
 import pytest
 import torch
 
@@ -35,7 +35,12 @@ def test_autotune_keeps_a_timed_configuration():
     table = p.autotune(reps=2)
     say("[tune] " + ", ".join(f"{t['chunks']}/{t['p1_lines']}/{t['z_lines']}: {t['ms']:.3f} ms" for t in table))
     assert len(table) == 4 * 2 * 2
-    best = min(table, key=lambda t: t["ms"])
+    # timing order; a later configuration replaces the best so far only when
+    # faster by more than 0.5 %
+    best = table[0]
+    for t in table[1:]:
+        if t["ms"] < best["ms"] * (1.0 - 0.005):
+            best = t
     assert (p.info["chunks"], p.info["p1_lines"], p.info["z_lines"]) == (best["chunks"], best["p1_lines"],
                                                                          best["z_lines"])
     a = p.make_ic(9)
