@@ -88,17 +88,20 @@ def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42, autotune=True, f
         plan.make_ic(seed + i, pos, vel, work=work)
     torch.cuda.synchronize()
     plan.timing_enable(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps: the mean over the whole loop and the
+    # median of the per-step intervals
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
+    marks[0].record()
     for i in range(steps):
         plan.make_ic(seed + i, pos, vel, work=work)
-    stop.record()
+        marks[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop) / steps
+    ms = marks[0].elapsed_time(marks[-1]) / steps
+    per_step = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
+    median = per_step[steps // 2] if steps % 2 else 0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2])
     pass_ms, calls = plan.timing_read()
     plan.timing_enable(False)
     chunks = plan.info["chunks"]
@@ -117,7 +120,8 @@ def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42, autotune=True, f
     chosen = {"chunks": plan.info["chunks"], "p1_lines": plan.info["p1_lines"], "z_lines": plan.info["z_lines"]}
     del pos, vel, work, plan
     torch.cuda.empty_cache()
-    return {"ms_per_step": ms, "wall_s": wall, "cells_per_s": n ** 3 / (ms * 1e-3), "passes": passes,
+    return {"ms_per_step": ms, "ms_median": median, "wall_s": wall, "cells_per_s": n ** 3 / (ms * 1e-3),
+            "cells_per_s_median": n ** 3 / (median * 1e-3), "passes": passes,
             "bytes_per_step": sum(nbytes), "chunks": chunks, "tuning": chosen,
             "autotune": [dict(t, ms=round(t["ms"], 3)) for t in tuning]}
 
@@ -205,6 +209,27 @@ def time_adjoint(gg, torch, n, box, dtype, steps, warmup, seed=42):
                     "fused into the first)"}
 
 
+def copy_peak(torch, gib=4, reps=10):
+    """Measured streaming rate of a plain float32 copy kernel (torch.mul by
+    1.0, gib GiB read and gib GiB written per launch), GB/s."""
+    count = gib * (1 << 30) // 4
+    src = torch.ones(count, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * count * 4 / (ms * 1e-3) / 1e9
+
+
 def calibrate_copy(torch, gib=1, reps=3):
     """A plain streaming kernel of known size for scaling the HBM counters:
     out = in * 1 over gib GiB of float32 (gib GiB read and gib GiB written
@@ -231,10 +256,24 @@ def cpu_baseline(n=256, box=500.0, min_seconds=10.0, max_reps=6):
         pipeline.make_ic(n, box, cosmology.Cosmology(), 42 + reps, workers=cores)
         reps += 1
     dt = time.perf_counter() - t0
+    # the same pipeline on one host thread, one 128^3 lattice
+    n1 = 128
+    t1 = time.perf_counter()
+    pipeline.make_ic(n1, box * n1 / n, cosmology.Cosmology(), 42, workers=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(reps * n ** 3 / dt, 1), "unit": "cells/s", "cores": cores, "kind": "oracle",
             "sample": f"full FP64 oracle pipeline (noise, rfftn, filter, 3 irfftn, particles) on {reps} "
                       f"{n}^3 lattices, box {box:g} Mpc/h, seeds 42..{41 + reps}; scipy.fft workers={cores}; "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "value_1_thread": round(n1 ** 3 / dt1, 1),
+            "sample_1_thread": f"one {n1}^3 lattice, workers=1, {dt1:.1f} s",
+            "cpu_model": model}
 
 
 def main():
@@ -268,6 +307,7 @@ def main():
         print(json.dumps(calibrate_copy(torch)), flush=True)
         return 0
     gg.lib()
+    copy_gbs = copy_peak(torch)
     fixed = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
     f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup, autotune=not args.no_autotune,
                     fixed=fixed)
@@ -281,9 +321,12 @@ def main():
     traffic = stored_traffic(dom["pass"], f32["tuning"]) if args.n == 1024 else None
     if traffic is not None:
         traffic = traffic / dom["launches"] if dom["launches"] > 1 else traffic
+    for p in f32["passes"]:
+        p["frac_copy"] = round(p["GB/s"] / copy_gbs, 4)
     roofline = {"bound": "hbm", "kernel": dom["pass"], "achieved": dom["GB/s"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": dom["frac_hbm"], "traffic": traffic,
-                "bytes_per_launch": dom["bytes_per_launch"], "ms_per_launch": dom["ms_per_launch"]}
+                "bytes_per_launch": dom["bytes_per_launch"], "ms_per_launch": dom["ms_per_launch"],
+                "copy_peak": round(copy_gbs, 1), "frac_copy": round(dom["GB/s"] / copy_gbs, 4)}
     out = {
         "metric": METRIC,
         "value": round(f32["cells_per_s"], 1),
@@ -292,6 +335,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(f32["ms_per_step"], 4),
+        "ms_per_step_median": round(f32["ms_median"], 4),
+        "value_median": round(f32["cells_per_s_median"], 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -308,7 +353,7 @@ def main():
     }
     if f64 is not None:
         out["fp64"] = {"value": round(f64["cells_per_s"], 1), "unit": "cells/s",
-                       "ms_per_step": round(f64["ms_per_step"], 4), "passes": f64["passes"], "tuning": f64["tuning"],
+                       "ms_per_step": round(f64["ms_per_step"], 4), "ms_per_step_median": round(f64["ms_median"], 4), "passes": f64["passes"], "tuning": f64["tuning"],
                        "fp32_speedup": round(f64["ms_per_step"] / f32["ms_per_step"], 3)}
     out["config"]["tuning"] = f32["tuning"]
     out["autotune"] = f32["autotune"]

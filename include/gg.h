@@ -269,6 +269,20 @@ gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t orig
 gg_status gg_lowpass(const gg_plan* plan, const void* field, int64_t n2_max, int32_t cic_deconvolve, void* out,
                      void* work, void* stream);
 
+/* Resolution degrade (Sec. 2.3, last paragraph): nearest-grid-point
+ * interpolation of a fine periodic field onto the plan's lattice, then a
+ * translation in Fourier space.  fine: (factor n)^3 reals of the plan dtype
+ * (row-major, axis 2 contiguous), factor in [1, 16]; the plan's lattice point
+ * m coincides with fine point factor * m and takes its value.  That field is
+ * then moved by shift[j] cells of the plan's lattice along axis j (the paper
+ * moves by half a coarse cell: shift = {0.5, 0.5, 0.5}): mode n_j (signed)
+ * is multiplied by exp(-2 pi i shift_j n_j / n), a Nyquist plane n_j = n/2 by
+ * cos(pi shift_j) (the real band-limited interpolant).  out: n^3 reals.
+ * work: gg_workspace_bytes(plan).  fine, out and work must not overlap.
+ * Apply per component to degrade a displacement field. */
+gg_status gg_degrade(const gg_plan* plan, const void* fine, int32_t factor, const double shift[3], void* out,
+                     void* work, void* stream);
+
 /* Eq. (3) for a lattice placed at origin (3 doubles, Mpc/h) inside a larger
  * periodic box: x_j = wrap(origin_j + (m_j + lattice_offset) L/N + psi_j) into
  * [0, wrap_box), velocities a H f psi_j.  A zoom level's particles in the base

@@ -94,6 +94,7 @@ _SIGS = {
                                               _VP]),
     "gg_lowpass": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP]),
     "gg_zeldovich_at": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP]),
+    "gg_degrade": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     "gg_zoom_create": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
     "gg_zoom_destroy": (ctypes.c_int, [_VP]),
     "gg_zoom_workspace_bytes": (ctypes.c_size_t, [_VP]),
@@ -325,6 +326,19 @@ class Plan:
             work = self.workspace()
         _check(lib().gg_lowpass(self._h, _ptr(field), int(n2_max), int(bool(deconvolve)), _ptr(out), _ptr(work),
                                 _stream()))
+        return out
+
+    def degrade(self, fine, factor, shift=(0.5, 0.5, 0.5), out=None, work=None):
+        """Sec. 2.3 degrade of a fine (factor n)^3 field onto this plan's lattice:
+        nearest-grid-point values, then a Fourier translation by ``shift``
+        coarse cells per axis."""
+        nf = self.n * int(factor)
+        fine = self._need(fine, (nf, nf, nf), self.real_dtype, "fine")
+        out = self._need(out, self._real_shape(), self.real_dtype, "out")
+        if work is None:
+            work = self.workspace()
+        sh = (ctypes.c_double * 3)(*[float(v) for v in shift])
+        _check(lib().gg_degrade(self._h, _ptr(fine), int(factor), sh, _ptr(out), _ptr(work), _stream()))
         return out
 
     def zeldovich_at(self, psi, origin, wrap_box, pos=None, vel=None):

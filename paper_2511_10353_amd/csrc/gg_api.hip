@@ -34,7 +34,8 @@ gg_status fail_hip(hipError_t e, const char* what) {
     return GG_ERR_HIP;
 }
 
-constexpr int kTimingSlots = 64;   // calls recorded per gg_timing_read
+constexpr int kTimingSlots = 64;
+constexpr int kMaxDegrade = 16;     // largest resolution-degrade factor   // calls recorded per gg_timing_read
 constexpr int kPasses = 5;
 constexpr int kMaxChunks = 8;
 constexpr int kLaunchesMax = 4 * kMaxChunks + 1;  // launches of one gg_make_ic
@@ -732,6 +733,33 @@ gg_status gg_lowpass(const gg_plan* pc, const void* field, int64_t n2_max, int32
             : gg::Ops<float>::lowpass(view<float>(pc), static_cast<const float*>(field), hi, cic_deconvolve ? 1 : 0,
                                       static_cast<float*>(out), static_cast<gg::cx<float>*>(work), s);
     return e == hipSuccess ? GG_OK : fail_hip(e, "lowpass launch");
+}
+
+gg_status gg_degrade(const gg_plan* pc, const void* fine, int32_t factor, const double shift[3], void* out, void* work,
+                     void* stream) {
+    if (!pc || !fine || !shift || !out || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_degrade");
+    if (factor < 1 || factor > kMaxDegrade) return fail(GG_ERR_INVALID_ARG, "factor must be in [1, 16]");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(shift[a]) || std::fabs(shift[a]) > 1e6)
+            return fail(GG_ERR_INVALID_ARG, "shift must be finite (|shift| <= 1e6 cells)");
+    if (!aligned(fine) || !aligned(out) || !aligned(work)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t es = elem_size(pc->dtype);
+    const size_t rb = (size_t)pc->n * pc->n * pc->n * es;
+    const size_t nf = (size_t)pc->n * factor;
+    const size_t fb = nf * nf * nf * es;
+    const size_t wb = gg_workspace_bytes(pc);
+    if (overlap(fine, fb, out, rb) || overlap(fine, fb, work, wb) || overlap(out, rb, work, wb))
+        return fail(GG_ERR_INVALID_ARG, "fine, out and work must not overlap");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e =
+        pc->dtype == GG_F64
+            ? gg::Ops<double>::degrade(view<double>(pc), static_cast<const double*>(fine), factor, shift,
+                                       static_cast<double*>(out), static_cast<gg::cx<double>*>(work), s)
+            : gg::Ops<float>::degrade(view<float>(pc), static_cast<const float*>(fine), factor, shift,
+                                      static_cast<float*>(out), static_cast<gg::cx<float>*>(work), s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "degrade launch");
 }
 
 gg_status gg_zeldovich_at(const gg_plan* pc, const void* psi, const double origin[3], double wrap_box, float* pos,

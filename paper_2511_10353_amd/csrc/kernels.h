@@ -696,6 +696,51 @@ __global__ void k_window(cx<T>* __restrict__ spec, int n, int n2_max, int deconv
 }
 
 // ---------------------------------------------------------------------------
+// Resolution degrade (Sec. 2.3): nearest-grid-point values of a periodic
+// fine field on the coarse lattice, whose point m coincides with fine point
+// factor * m ...
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_decimate(const T* __restrict__ fine, int n_lo, int factor, T* __restrict__ lo) {
+    const uint64_t total = (uint64_t)n_lo * n_lo * n_lo;
+    const uint64_t n_hi = (uint64_t)n_lo * factor;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t m2 = i % n_lo, r = i / n_lo;
+        const uint64_t m1 = r % n_lo, m0 = r / n_lo;
+        lo[i] = fine[((m0 * factor) * n_hi + m1 * factor) * n_hi + m2 * factor];
+    }
+}
+
+// ... then moved by s_j coarse cells along axis j in Fourier space: mode n
+// (signed) gets exp(-2 pi i s n / N) per axis, the Nyquist plane cos(pi s)
+// (the real band-limited interpolant), on a plain half spectrum.
+template <typename T>
+__device__ __forceinline__ cx<T> translate_factor(int k, int n, double s) {
+    if (2 * k == n) return {(T)cospi(s), (T)0};
+    const int sk = k <= n / 2 ? k : k - n;
+    double a = -2.0 * s * (double)sk / (double)n;  // angle in units of pi
+    a -= 2.0 * rint(0.5 * a);                      // into [-1, 1]
+    T sn, cs;
+    if constexpr (sizeof(T) == 4) sincospif((float)a, &sn, &cs);
+    else sincospi(a, &sn, &cs);
+    return {cs, sn};
+}
+
+template <typename T>
+__global__ void k_translate(cx<T>* __restrict__ spec, int n, double s0, double s1, double s2) {
+    const int K = n / 2 + 1;
+    const uint64_t total = (uint64_t)n * n * K;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int k2 = (int)(i % K);
+        const uint64_t r = i / K;
+        const int k1 = (int)(r % n), k0 = (int)(r / n);
+        const cx<T> f = cmul(cmul(translate_factor<T>(k0, n, s0), translate_factor<T>(k1, n, s1)),
+                             translate_factor<T>(k2, n, s2));
+        spec[i] = cmul(spec[i], f);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Stand-alone Eq. (1)-(2) on a full half spectrum (k2 in [0, N/2]).
 // tau here carries the 1/N^3 of the fused path; scale = N^3 removes it.
 // ---------------------------------------------------------------------------

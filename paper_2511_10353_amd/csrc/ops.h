@@ -78,6 +78,10 @@ struct Ops {
     // deconvolution; out (R) may equal field; work: two plain half spectra
     static hipError_t lowpass(const PlanView<T>& pv, const T* field, int n2_max, int deconv, T* out, cx<T>* work,
                               hipStream_t s);
+    // Sec. 2.3 degrade: NGP values of the (factor n)^3 fine field on the plan's
+    // lattice, moved by shift[j] coarse cells along axis j in Fourier space
+    static hipError_t degrade(const PlanView<T>& pv, const T* fine, int factor, const double shift[3], T* out,
+                              cx<T>* work, hipStream_t s);
     static hipError_t fused_forward(const PlanView<T>& pv, const T* w, uint64_t seed, float* pos, float* vel, T* psi,
                                     cx<T>* work, const ExecCtx& x);
     // chunk count the fused path can use for lattice n (1 = no pipelining)

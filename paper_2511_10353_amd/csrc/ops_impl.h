@@ -472,6 +472,21 @@ hipError_t Ops<T>::lowpass(const PlanView<T>& pv, const T* field, int n2_max, in
 }
 
 template <typename T>
+hipError_t Ops<T>::degrade(const PlanView<T>& pv, const T* fine, int factor, const double shift[3], T* out,
+                           cx<T>* work, hipStream_t s) {
+    const int n = pv.n;
+    const uint64_t n3 = (uint64_t)n * n * n;
+    const size_t hsz = (size_t)n * n * (n / 2 + 1);
+    k_decimate<T><<<capped_grid(n3, 256), 256, 0, s>>>(fine, n, factor, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = fft_forward(pv, out, work, s)) != hipSuccess) return e;
+    k_translate<T><<<capped_grid(hsz, 256), 256, 0, s>>>(work, n, shift[0], shift[1], shift[2]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return fft_inverse(pv, work, out, work + hsz, s);
+}
+
+template <typename T>
 hipError_t Ops<T>::tau_table(T* tau, int64_t ntau, float4* tauseg, int n, double box, double amp_growth2,
                              double gamma, double n_s, hipStream_t s) {
     k_tau<T><<<capped_grid((uint64_t)ntau, 256), 256, 0, s>>>(tau, ntau, n, box, amp_growth2, gamma, n_s);
