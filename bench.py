@@ -256,10 +256,10 @@ def cpu_baseline(n=256, box=500.0, min_seconds=10.0, max_reps=6):
         pipeline.make_ic(n, box, cosmology.Cosmology(), 42 + reps, workers=cores)
         reps += 1
     dt = time.perf_counter() - t0
-    # the same pipeline on one host thread, one 128^3 lattice
-    n1 = 128
+    # the same pipeline on one host thread, one lattice of the same size
+    n1 = n
     t1 = time.perf_counter()
-    pipeline.make_ic(n1, box * n1 / n, cosmology.Cosmology(), 42, workers=1)
+    pipeline.make_ic(n1, box, cosmology.Cosmology(), 42, workers=1)
     dt1 = time.perf_counter() - t1
     model = ""
     try:

@@ -73,10 +73,27 @@ def test_fp32_matches_fp64_at_1024():
     torch.cuda.empty_cache()
 
 
+def _oracle_noise(n, seed, dtype, workers, slabs=16):
+    """The oracle's noise field, filled slab by slab (axis 0) with a line per slab."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import noise as onoise
+    out = np.empty((n, n, n), dtype=dtype)
+    flat = out.reshape(-1)
+    per = n // slabs * n * n
+    chunk = 1 << 22
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for s in range(slabs):
+            def fill(a, s=s):
+                b = min(a + chunk, (s + 1) * per)
+                flat[a:b] = onoise.noise_cells(np.arange(a, b, dtype=np.uint64), seed, 0, dtype)
+            list(ex.map(fill, range(s * per, (s + 1) * per, chunk)))
+            say(f"[1024 oracle] noise slab {s + 1}/{slabs}")
+    return out
+
+
 @pytest.mark.slow
 def test_1024_against_fp64_oracle():
     from oracle import cosmology as ocosmo
-    from oracle import noise as onoise
     from oracle import pipeline as opipe
     workers = min(16, os.cpu_count() or 1)
     c = ocosmo.Cosmology()
@@ -90,7 +107,7 @@ def test_1024_against_fp64_oracle():
         torch.cuda.synchronize()
         p.close()
         say(f"[1024 oracle] oracle noise {dtype} ({workers} threads)")
-        w = onoise.noise_grid(N, SEED, dtype=np.float32 if dtype == "f32" else np.float64, workers=workers)
+        w = _oracle_noise(N, SEED, np.float32 if dtype == "f32" else np.float64, workers)
         w_hat = opipe.forward(w.astype(np.float64), workers=workers)
         del w
         d_hat = opipe.density_spectrum(w_hat, N, BOX, c)
