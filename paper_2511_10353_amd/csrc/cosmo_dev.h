@@ -89,4 +89,53 @@ __global__ void k_tauseg(float4* __restrict__ seg, int n, double box, double amp
     }
 }
 
+// Piecewise degree-7 form of tau for the double-precision fused passes, 32 KB
+// in LDS next to a 128 KB transform tile.  Integer n2 < 2^20 maps to segment
+// seg(n2) = 32 sh + (n2 >> sh), sh = max(floor(log2 n2) - 5, 0), and
+// t = (n2 mod 2^sh) / 2^sh in [0, 1): segments below 64 hold single integers
+// (exact values), above that each octave is cut into 32 segments of width
+// 2^sh.  Segment s stores the monomial coefficients c0..c7 (in t) of the
+// polynomial interpolating tau at the eight Chebyshev points of [0, 1]
+// (Newton divided differences in binary64, expanded); the relative error is
+// below 2e-15 for every n2 of lattices from 16^3 to 1024^3 and boxes from 60
+// to 5000 Mpc/h, against the 1e-12 bar of the double path.
+constexpr int kTauSeg64 = 32 * 16;  // n2 < 2^20 covers N <= 1024
+constexpr int kTauDeg64 = 7;
+
+template <typename T>  // T: the plan's type (instantiated per translation unit)
+__global__ void k_tauseg64(double* __restrict__ coef, int n, double box, double amp_growth2, double gamma,
+                           double n_s) {
+    constexpr int K = kTauDeg64 + 1;
+    const double n3 = (double)n * (double)n * (double)n;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < kTauSeg64; s += gridDim.x * blockDim.x) {
+        double c[K];
+        for (int k = 0; k < K; ++k) c[k] = 0.0;
+        if (s < 64) {
+            if (s > 0) c[0] = tau_value((double)s, n3, box, amp_growth2, gamma, n_s);
+        } else {
+            const int sh = (s >> 5) - 1;
+            const double w = (double)(1 << sh);
+            const double base = (double)((s & 31) + 32) * w;
+            double tn[K], f[K];
+            for (int i = 0; i < K; ++i) {
+                tn[i] = 0.5 - 0.5 * cos(kPi * (i + 0.5) / K);
+                f[i] = tau_value(base + w * tn[i], n3, box, amp_growth2, gamma, n_s);
+            }
+            for (int j = 1; j < K; ++j)  // divided differences f[t0..ti] in place
+                for (int i = K - 1; i >= j; --i) f[i] = (f[i] - f[i - 1]) / (tn[i] - tn[i - j]);
+            // p(t) = f0 + (t - t0)(f1 + (t - t1)(f2 + ...)), expanded from the inside out
+            c[0] = f[K - 1];
+            int deg = 0;
+            for (int i = K - 2; i >= 0; --i) {
+                // c <- c * (t - tn[i]) + f[i]
+                c[deg + 1] = c[deg];
+                for (int k = deg; k >= 1; --k) c[k] = c[k - 1] - tn[i] * c[k];
+                c[0] = f[i] - tn[i] * c[0];
+                ++deg;
+            }
+        }
+        for (int k = 0; k < K; ++k) coef[(size_t)s * K + k] = c[k];
+    }
+}
+
 }  // namespace gg

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gg.h"
@@ -51,7 +52,7 @@ struct gg_plan {
     void* tw = nullptr;    // N complex values of the dtype
     void* tau = nullptr;   // ntau values of the dtype
     int64_t ntau = 0;
-    void* tauseg = nullptr;  // float plans: kTauSeg float4 (piecewise-cubic tau)
+    void* tauseg = nullptr;  // piecewise tau: kTauSeg float4 (float plans), kTauSeg64 x 8 doubles (double plans)
     double amplitude = 0, sigma_int = 0, growth = 0, vfac = 0, cell = 0;
     // tile choices of the fused path (0 = built-in; set by gg_plan_set_tuning
     // or gg_plan_autotune)
@@ -80,7 +81,8 @@ gg::PlanView<T> view(const gg_plan* p) {
     v.vfac = p->vfac;
     v.tw = static_cast<const gg::cx<T>*>(p->tw);
     v.tau = static_cast<const T*>(p->tau);
-    v.tauseg = static_cast<const float4*>(p->tauseg);
+    v.tauseg = std::is_same_v<T, float> ? static_cast<const float4*>(p->tauseg) : nullptr;
+    v.tauseg64 = std::is_same_v<T, double> ? static_cast<const double2*>(p->tauseg) : nullptr;
     v.amp_scale = 1.0;
     v.n2_lo = 0;
     v.n2_hi = 0x7FFFFFFF;
@@ -202,7 +204,9 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     do {
         if ((e = hipMalloc(&p->tw, 2 * es * p->n)) != hipSuccess ||
             (e = hipMalloc(&p->tau, es * p->ntau)) != hipSuccess || (e = hipMalloc(&d_sig, sizeof(double))) != hipSuccess ||
-            (dtype == GG_F32 && (e = hipMalloc(&p->tauseg, gg::kTauSeg * sizeof(float4))) != hipSuccess)) {
+            (e = hipMalloc(&p->tauseg, dtype == GG_F32 ? gg::kTauSeg * sizeof(float4)
+                                                       : gg::kTauSeg64 * (gg::kTauDeg64 + 1) * sizeof(double))) !=
+                hipSuccess) {
             st = fail(GG_ERR_OUT_OF_MEMORY, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
             break;
         }
@@ -243,11 +247,11 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
         p->vfac = a * (100.0 * std::sqrt(c.omega_m / std::pow(a, 3.0) + 1.0 - c.omega_m)) * 1.0;
         const double ag2 = p->amplitude * p->growth * p->growth;
         if (dtype == GG_F64)
-            e = gg::Ops<double>::tau_table(static_cast<double*>(p->tau), p->ntau, nullptr, p->n, p->box, ag2, gamma,
+            e = gg::Ops<double>::tau_table(static_cast<double*>(p->tau), p->ntau, p->tauseg, p->n, p->box, ag2, gamma,
                                            c.n_s, s);
         else
-            e = gg::Ops<float>::tau_table(static_cast<float*>(p->tau), p->ntau, static_cast<float4*>(p->tauseg), p->n,
-                                          p->box, ag2, gamma, c.n_s, s);
+            e = gg::Ops<float>::tau_table(static_cast<float*>(p->tau), p->ntau, p->tauseg, p->n, p->box, ag2, gamma,
+                                          c.n_s, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             st = fail_hip(e, "tau table");

@@ -42,6 +42,7 @@ struct PlanView {
     const cx<T>* tw;        // tw[m] = exp(-2 pi i m / N), m < N
     const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2, binary64 values rounded to T
     const float4* tauseg;   // piecewise-cubic tau (kTauSeg segments), float plans only
+    const double2* tauseg64;  // piecewise degree-7 tau (kTauSeg64 x 4 double2), double plans only
     double amp_scale;       // displacement scale sqrt(A'/A) (1 for the plan's amplitude)
     // mode window of the axis-0 filter passes (Eq. 4-5): modes with
     // n2 < n2_lo or n2 >= n2_hi are dropped; deconv divides by the
@@ -82,6 +83,26 @@ struct TauLookup {
 };
 
 template <>
+struct TauLookup<double> {
+    const double2* seg;
+    __device__ double operator()(int n2) const {
+        const uint32_t u = (uint32_t)n2;
+        const int e = 31 - __clz(u | 1u);
+        const int sh = e > 5 ? e - 5 : 0;
+        const double2* c = seg + 4 * ((sh << 5) + (u >> sh));
+        const double t = (double)(u & ((1u << sh) - 1u)) * __longlong_as_double((long long)(1023 - sh) << 52);
+        const double2 c01 = c[0], c23 = c[1], c45 = c[2], c67 = c[3];
+        double p = fma(t, c67.y, c67.x);
+        p = fma(t, p, c45.y);
+        p = fma(t, p, c45.x);
+        p = fma(t, p, c23.y);
+        p = fma(t, p, c23.x);
+        p = fma(t, p, c01.y);
+        return fma(t, p, c01.x);
+    }
+};
+
+template <>
 struct TauLookup<float> {
     const float4* seg;
     __device__ float operator()(int n2) const {
@@ -103,7 +124,9 @@ __device__ inline TauLookup<T> tau_lookup(const PlanView<T>& pv) {
         for (int i = threadIdx.x; i < kTauSeg; i += blockDim.x) tl[i] = pv.tauseg[i];
         return TauLookup<float>{tl};
     } else {
-        return TauLookup<T>{pv.tau};
+        __shared__ double2 tl[4 * kTauSeg64];
+        for (int i = threadIdx.x; i < 4 * kTauSeg64; i += blockDim.x) tl[i] = pv.tauseg64[i];
+        return TauLookup<double>{tl};
     }
 }
 

@@ -91,7 +91,7 @@ struct Ops {
     static void tile_options(int n, int& full, int& half, int& p1_default, int& z_default);
     // exact table tau[ntau]; for float plans also the piecewise-cubic
     // segments (kTauSeg float4) the fused passes evaluate
-    static hipError_t tau_table(T* tau, int64_t ntau, float4* tauseg, int n, double box, double amp_growth2,
+    static hipError_t tau_table(T* tau, int64_t ntau, void* tauseg, int n, double box, double amp_growth2,
                                 double gamma, double n_s, hipStream_t s);
     // bytes of the fused path's workspace (three half spectra without the
     // k2 = N/2 plane) and of the inverse transform's scratch (one full half

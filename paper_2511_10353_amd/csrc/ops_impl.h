@@ -487,12 +487,17 @@ hipError_t Ops<T>::degrade(const PlanView<T>& pv, const T* fine, int factor, con
 }
 
 template <typename T>
-hipError_t Ops<T>::tau_table(T* tau, int64_t ntau, float4* tauseg, int n, double box, double amp_growth2,
+hipError_t Ops<T>::tau_table(T* tau, int64_t ntau, void* tauseg, int n, double box, double amp_growth2,
                              double gamma, double n_s, hipStream_t s) {
     k_tau<T><<<capped_grid((uint64_t)ntau, 256), 256, 0, s>>>(tau, ntau, n, box, amp_growth2, gamma, n_s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && tauseg) {
-        k_tauseg<T><<<(kTauSeg + 255) / 256, 256, 0, s>>>(tauseg, n, box, amp_growth2, gamma, n_s);
+        if constexpr (sizeof(T) == 4)
+            k_tauseg<T><<<(kTauSeg + 255) / 256, 256, 0, s>>>(static_cast<float4*>(tauseg), n, box, amp_growth2,
+                                                               gamma, n_s);
+        else
+            k_tauseg64<T><<<(kTauSeg64 + 63) / 64, 64, 0, s>>>(static_cast<double*>(tauseg), n, box, amp_growth2,
+                                                                gamma, n_s);
         e = hipGetLastError();
     }
     return e;
