@@ -1066,9 +1066,16 @@ gg_status zoom_sequence(gg_zoom* z, uint64_t seed, void* const* w, void* const* 
                                     w[l], stream))
         GG_Z(gg_make_displacements(z->plans[l], w[l], zoom_cut(z->box[l], r_s), 0, 0, psi[l], work, stream))
         const size_t rp = es * (size_t)np * np * np;
-        for (int j = 0; j < 3; ++j)
-            GG_Z(gg_lowpass(z->plans[l - 1], static_cast<char*>(psi[l - 1]) + j * rp, zoom_cut(z->box[l - 1], r_s), 1,
-                            static_cast<char*>(tmp) + j * rp, work, stream))
+        if (l == 1) {
+            // the base displacements are the filtered base noise, so Eq. 5 of them
+            // is that filter on the large-scale window: one fused pass sequence
+            // over the base noise instead of three transform round trips
+            GG_Z(gg_make_displacements(z->plans[0], w[0], 0, zoom_cut(z->box[0], r_s), 1, tmp, work, stream))
+        } else {
+            for (int j = 0; j < 3; ++j)
+                GG_Z(gg_lowpass(z->plans[l - 1], static_cast<char*>(psi[l - 1]) + j * rp, zoom_cut(z->box[l - 1], r_s),
+                                1, static_cast<char*>(tmp) + j * rp, work, stream))
+        }
         GG_Z(gg_interpolate_add_at(np, 2, d.origin[l], n, z->dtype, tmp, psi[l], stream))
         GG_Z(gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], stream))
     }
