@@ -9,7 +9,6 @@ resident in HBM.  The default workload is the 1024^3 lattice in a
 timed beside it.  Prints one JSON line.
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -26,10 +25,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_1024cubed_f32.md")
 
 
+# sources of the fused path's kernels and their launch configuration
+KERNEL_SOURCES = ["cosmo_dev.h", "fft_core.h", "kernels.h", "noise_dev.h", "ops.h", "ops_impl.h"]
+
+
 def kernel_source_hash():
-    """sha256 over the HIP sources, to tell whether stored counters still apply."""
+    """sha256 over the sources of the fused path's kernels, to tell whether
+    stored counters still apply."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2511_10353_amd", "csrc", "*"))):
+    for path in [os.path.join(ROOT, "paper_2511_10353_amd", "csrc", f) for f in KERNEL_SOURCES]:
         h.update(os.path.basename(path).encode())
         with open(path, "rb") as f:
             h.update(f.read())
@@ -45,7 +49,7 @@ def stored_traffic(pass_name, tuning):
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
+    m = re.search(r"kernel sources sha256[^:]*: ([0-9a-f]{64})", text)
     if not m or m.group(1) != kernel_source_hash():
         return None
     m = re.search(r"tuning: chunks=(\d+) p1_lines=(\d+) z_lines=(\d+)", text)
