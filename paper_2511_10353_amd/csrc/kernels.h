@@ -704,12 +704,12 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_window(cx<T>* __restrict__ spec, int n, int n2_max, int deconv) {
-    const int K = n / 2 + 1;
-    const uint64_t total = (uint64_t)n * n * K;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t K = n / 2 + 1;
+    const uint32_t total = (uint32_t)n * n * K;  // < 2^30 for n <= 1024
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const int k2 = (int)(i % K);
-        const uint64_t r = i / K;
-        const int k1 = (int)(r % n), k0 = (int)(r / n);
+        const uint32_t r = i / K;
+        const int k1 = (int)(r % (uint32_t)n), k0 = (int)(r / (uint32_t)n);
         const int s0 = k0 <= n / 2 ? k0 : k0 - n, s1 = k1 <= n / 2 ? k1 : k1 - n;
         const int n2 = s0 * s0 + s1 * s1 + k2 * k2;
         T f = n2 < n2_max ? (T)1 : (T)0;
@@ -751,12 +751,12 @@ __device__ __forceinline__ cx<T> translate_factor(int k, int n, double s) {
 
 template <typename T>
 __global__ void k_translate(cx<T>* __restrict__ spec, int n, double s0, double s1, double s2) {
-    const int K = n / 2 + 1;
-    const uint64_t total = (uint64_t)n * n * K;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t K = n / 2 + 1;
+    const uint32_t total = (uint32_t)n * n * K;  // < 2^30 for n <= 1024
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const int k2 = (int)(i % K);
-        const uint64_t r = i / K;
-        const int k1 = (int)(r % n), k0 = (int)(r / n);
+        const uint32_t r = i / K;
+        const int k1 = (int)(r % (uint32_t)n), k0 = (int)(r / (uint32_t)n);
         const cx<T> f = cmul(cmul(translate_factor<T>(k0, n, s0), translate_factor<T>(k1, n, s1)),
                              translate_factor<T>(k2, n, s2));
         spec[i] = cmul(spec[i], f);
@@ -795,18 +795,16 @@ __global__ void k_filter(const cx<T>* __restrict__ w, cx<T>* __restrict__ psi, c
 template <typename T>
 __global__ void k_zeldovich(const T* __restrict__ psi, float* __restrict__ pos, float* __restrict__ vel,
                             PlanView<T> pv) {
+    // block: one lattice row (m0, m1) = blockIdx.x and a run of m2; comp = blockIdx.z
     const int n = pv.n;
-    const uint64_t n3 = (uint64_t)n * n * n;
-    for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < 3 * n3;
-         idx += (uint64_t)gridDim.x * blockDim.x) {
-        const int comp = (int)(idx / n3);
-        const uint64_t cell = idx % n3;
-        int m;
-        if (comp == 0) m = (int)(cell / ((uint64_t)n * n));
-        else if (comp == 1) m = (int)((cell / n) % n);
-        else m = (int)(cell % n);
-        zel_point<T>(psi[idx], m, pv.origin[comp], pv.cell, pv.offset, pv.wrap, (T)pv.vfac, pos[idx], vel[idx]);
-    }
+    const int m2 = blockIdx.y * blockDim.x + threadIdx.x;
+    if (m2 >= n) return;
+    const int row = blockIdx.x;
+    const int m0 = row / n, m1 = row - m0 * n;
+    const int comp = blockIdx.z;
+    const uint64_t idx = (uint64_t)comp * n * n * n + (uint64_t)row * n + m2;
+    const int m = comp == 0 ? m0 : (comp == 1 ? m1 : m2);
+    zel_point<T>(psi[idx], m, pv.origin[comp], pv.cell, pv.offset, pv.wrap, (T)pv.vfac, pos[idx], vel[idx]);
 }
 
 }  // namespace gg

@@ -160,8 +160,8 @@ hipError_t Ops<T>::filter(const PlanView<T>& pv, const cx<T>* w, cx<T>* psi, cx<
 
 template <typename T>
 hipError_t Ops<T>::zeldovich(const PlanView<T>& pv, const T* psi, float* pos, float* vel, hipStream_t s) {
-    const uint64_t n3 = (uint64_t)pv.n * pv.n * pv.n;
-    k_zeldovich<T><<<capped_grid(3 * n3, 256), 256, 0, s>>>(psi, pos, vel, pv);
+    const unsigned bz = pv.n < 256 ? (unsigned)((pv.n + 63) / 64 * 64) : 256u;
+    k_zeldovich<T><<<dim3((unsigned)(pv.n * pv.n), (unsigned)((pv.n + bz - 1) / bz), 3), bz, 0, s>>>(psi, pos, vel, pv);
     return hipGetLastError();
 }
 
@@ -453,9 +453,10 @@ hipError_t Ops<T>::cic_add(const T* src, int n_src, int ratio, const int origin[
     if (n_src < 1 || n_dst < 1 || ratio < 1) return hipErrorInvalidValue;
     for (int a = 0; a < 3; ++a)
         if (origin[a] < 0 || origin[a] >= n_src) return hipErrorInvalidValue;
-    const uint64_t n3 = (uint64_t)n_dst * n_dst * n_dst;
-    k_cic_add<T><<<dim3(capped_grid(n3, 256), 3), 256, 0, s>>>(src, n_src, ratio, origin[0], origin[1], origin[2], dst,
-                                                               n_dst);
+    if (n_dst > 4096) return hipErrorInvalidValue;
+    const unsigned bc = n_dst < 256 ? (unsigned)((n_dst + 63) / 64 * 64) : 256u;
+    k_cic_add<T><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc), 3), bc, 0, s>>>(
+        src, n_src, ratio, origin[0], origin[1], origin[2], dst, n_dst);
     return hipGetLastError();
 }
 

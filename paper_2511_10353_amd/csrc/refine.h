@@ -212,27 +212,29 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
 template <typename T>
 __global__ void k_cic_add(const T* __restrict__ src, int ns, int R, int o0, int o1, int o2, T* __restrict__ dst,
                           int nd) {
+    // block: one destination row (x, y) = blockIdx.x and a run of z; comp = blockIdx.z
+    const int z = blockIdx.y * blockDim.x + threadIdx.x;
+    if (z >= nd) return;
+    const int row = blockIdx.x;
+    const int x = row / nd, y = row - x * nd;
     const uint64_t n3d = (uint64_t)nd * nd * nd;
     const uint64_t n3s = (uint64_t)ns * ns * ns;
-    const int comp = blockIdx.y;
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n3d; c += (uint64_t)gridDim.x * blockDim.x) {
-        const int z = (int)(c % nd), y = (int)((c / nd) % nd), x = (int)(c / ((uint64_t)nd * nd));
-        const int x0 = (o0 + x / R) % ns, y0 = (o1 + y / R) % ns, z0 = (o2 + z / R) % ns;
-        const double tx = (double)(x % R) / R, ty = (double)(y % R) / R, tz = (double)(z % R) / R;
-        const int x1 = (x0 + 1) % ns, y1 = (y0 + 1) % ns, z1 = (z0 + 1) % ns;
-        const T* s = src + comp * n3s;
-        auto at = [&](int i, int j, int k) { return (double)s[((uint64_t)i * ns + j) * ns + k]; };
-        // interpolate along axis 0, then 1, then 2 (the oracle's order)
-        const double a00 = at(x0, y0, z0) * (1.0 - tx) + at(x1, y0, z0) * tx;
-        const double a10 = at(x0, y1, z0) * (1.0 - tx) + at(x1, y1, z0) * tx;
-        const double a01 = at(x0, y0, z1) * (1.0 - tx) + at(x1, y0, z1) * tx;
-        const double a11 = at(x0, y1, z1) * (1.0 - tx) + at(x1, y1, z1) * tx;
-        const double b0 = a00 * (1.0 - ty) + a10 * ty;
-        const double b1 = a01 * (1.0 - ty) + a11 * ty;
-        const double v = b0 * (1.0 - tz) + b1 * tz;
-        T* d = dst + comp * n3d + c;
-        *d = (T)((double)*d + v);
-    }
+    const int comp = blockIdx.z;
+    const int x0 = (o0 + x / R) % ns, y0 = (o1 + y / R) % ns, z0 = (o2 + z / R) % ns;
+    const double tx = (double)(x % R) / R, ty = (double)(y % R) / R, tz = (double)(z % R) / R;
+    const int x1 = x0 + 1 == ns ? 0 : x0 + 1, y1 = y0 + 1 == ns ? 0 : y0 + 1, z1 = z0 + 1 == ns ? 0 : z0 + 1;
+    const T* s = src + comp * n3s;
+    auto at = [&](int i, int j, int k) { return (double)s[((uint64_t)i * ns + j) * ns + k]; };
+    // interpolate along axis 0, then 1, then 2 (the oracle's order)
+    const double a00 = at(x0, y0, z0) * (1.0 - tx) + at(x1, y0, z0) * tx;
+    const double a10 = at(x0, y1, z0) * (1.0 - tx) + at(x1, y1, z0) * tx;
+    const double a01 = at(x0, y0, z1) * (1.0 - tx) + at(x1, y0, z1) * tx;
+    const double a11 = at(x0, y1, z1) * (1.0 - tx) + at(x1, y1, z1) * tx;
+    const double b0 = a00 * (1.0 - ty) + a10 * ty;
+    const double b1 = a01 * (1.0 - ty) + a11 * ty;
+    const double v = b0 * (1.0 - tz) + b1 * tz;
+    T* d = dst + comp * n3d + (uint64_t)row * nd + z;
+    *d = (T)((double)*d + v);
 }
 
 }  // namespace gg
