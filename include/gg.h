@@ -250,9 +250,12 @@ gg_status gg_make_displacements(const gg_plan* plan, const void* w, int64_t n2_m
                                 int32_t cic_deconvolve, void* psi, void* work, void* stream);
 
 /* dst (3 fields of n_dst^3) += cloud-in-cell (trilinear, periodic)
- * interpolation of src (3 fields of n_src^3) to the points m L / n_dst; n_dst
- * is a multiple of n_src; sums in binary64.  The large-scale half of Eq. 4-5
- * on the fine lattice. */
+ * interpolation of src (3 fields of n_src^3) to the points m L / n_dst,
+ * 1 <= n_src <= n_dst <= 4096 (any ratio: a multiple for factor-2 refinement,
+ * 3/2 for the three-cell patches of Eq. A.15); point m lies in source cell
+ * floor(m n_src / n_dst) with weight ((m n_src) mod n_dst) / n_dst, both
+ * exact; sums in binary64.  The large-scale half of Eq. 4-5 on the fine
+ * lattice. */
 gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream);
 
 /* dst (3 fields of n_dst^3) += cloud-in-cell interpolation of the periodic

@@ -154,15 +154,40 @@ def cic_upsample(field, ratio):
     return out
 
 
+def cic_resample(field, n_out):
+    """Trilinear (cloud-in-cell) interpolation of a periodic field of n^3
+    points to the n_out^3 points of the same box (any n_out >= 1): point m
+    sits at u = m n / n_out source cells, split exactly into the cell
+    floor(m n / n_out) and the weight ((m n) mod n_out) / n_out; axis 0, then
+    1, then 2."""
+    f = np.asarray(field, dtype=np.float64)
+    n = f.shape[0]
+    mn = np.arange(n_out, dtype=np.int64) * n
+    i0 = mn // n_out
+    t = (mn % n_out) / float(n_out)
+    i1 = (i0 + 1) % n
+    out = f
+    for axis in range(3):
+        a = np.take(out, i0, axis=axis)
+        b = np.take(out, i1, axis=axis)
+        shape = [1, 1, 1]
+        shape[axis] = n_out
+        tt = t.reshape(shape)
+        out = a * (1.0 - tt) + b * tt
+    return out
+
+
 def combine(w_parent, w_child, box, cosmo, r_s, workers=None):
     """Full-box resolution increase: psi on the child grid from the parent's
     large scales (Eq. 5, CiC with deconvolution) and the child's small scales
-    (Eq. 4)."""
+    (Eq. 4).  A child a whole multiple of the parent uses cic_upsample, any
+    other size (the 3/2 patches of Eq. A.15) cic_resample."""
     n_p = np.asarray(w_parent).shape[0]
     n_c = np.asarray(w_child).shape[0]
-    if n_c % n_p:
-        raise ValueError("child size must be a multiple of the parent size")
-    ratio = n_c // n_p
+    if n_c < n_p:
+        raise ValueError("child lattice smaller than the parent")
     small = windowed_displacements(w_child, n_c, box, cosmo, r_s, "small", workers=workers)
     large = windowed_displacements(w_parent, n_p, box, cosmo, r_s, "large", deconvolve=True, workers=workers)
-    return small + np.stack([cic_upsample(large[j], ratio) for j in range(3)])
+    if n_c % n_p == 0:
+        return small + np.stack([cic_upsample(large[j], n_c // n_p) for j in range(3)])
+    return small + np.stack([cic_resample(large[j], n_c) for j in range(3)])

@@ -690,12 +690,11 @@ gg_status gg_make_displacements(const gg_plan* pc, const void* w, int64_t n2_min
     return e == hipSuccess ? GG_OK : fail_hip(e, "make_displacements launch");
 }
 
-gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t origin[3], int32_t n_dst, gg_dtype dtype,
-                                const void* src, void* dst, void* stream) {
-    if (!src || !dst || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add_at");
-    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
-    if (n_src < 1 || n_src > 4096 || n_dst < 1 || n_dst > 4096 || ratio < 1 || ratio > 64)
-        return fail(GG_ERR_INVALID_ARG, "sizes in [1, 4096], ratio in [1, 64]");
+namespace {
+
+// dst += CiC interpolation of src at origin + m num / den source cells (validated sizes)
+gg_status interpolate_add_step(int32_t n_src, int32_t num, int32_t den, const int32_t origin[3], int32_t n_dst,
+                               gg_dtype dtype, const void* src, void* dst, void* stream) {
     for (int a = 0; a < 3; ++a)
         if (origin[a] < 0 || origin[a] >= n_src) return fail(GG_ERR_INVALID_ARG, "origin must be in [0, n_src)");
     if (!aligned(src) || !aligned(dst)) return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
@@ -704,18 +703,38 @@ gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t orig
         return fail(GG_ERR_INVALID_ARG, "src and dst must not overlap");
     const int o[3] = {origin[0], origin[1], origin[2]};
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t e = dtype == GG_F64 ? gg::Ops<double>::cic_add(static_cast<const double*>(src), n_src, ratio, o,
-                                                                   static_cast<double*>(dst), n_dst, s)
-                                         : gg::Ops<float>::cic_add(static_cast<const float*>(src), n_src, ratio, o,
-                                                                  static_cast<float*>(dst), n_dst, s);
+    const hipError_t e =
+        dtype == GG_F64 ? gg::Ops<double>::cic_add(static_cast<const double*>(src), n_src, num, den, o,
+                                                   static_cast<double*>(dst), n_dst, s)
+                        : gg::Ops<float>::cic_add(static_cast<const float*>(src), n_src, num, den, o,
+                                                  static_cast<float*>(dst), n_dst, s);
     return e == hipSuccess ? GG_OK : fail_hip(e, "interpolate_add launch");
 }
 
+}  // namespace
+
+gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t origin[3], int32_t n_dst, gg_dtype dtype,
+                                const void* src, void* dst, void* stream) {
+    if (!src || !dst || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add_at");
+    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    if (n_src < 1 || n_src > 4096 || n_dst < 1 || n_dst > 4096 || ratio < 1 || ratio > 64)
+        return fail(GG_ERR_INVALID_ARG, "sizes in [1, 4096], ratio in [1, 64]");
+    return interpolate_add_step(n_src, 1, ratio, origin, n_dst, dtype, src, dst, stream);
+}
+
 gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream) {
-    if (n_src < 1 || n_dst < n_src || n_dst % n_src)
-        return fail(GG_ERR_INVALID_ARG, "n_dst must be a multiple of n_src");
+    if (!src || !dst) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add");
+    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    if (n_src < 1 || n_src > 4096 || n_dst < n_src || n_dst > 4096)
+        return fail(GG_ERR_INVALID_ARG, "sizes must satisfy 1 <= n_src <= n_dst <= 4096");
+    int32_t a = n_src, b = n_dst;
+    while (b) {
+        const int32_t r = a % b;
+        a = b;
+        b = r;
+    }
     const int32_t origin[3] = {0, 0, 0};
-    return gg_interpolate_add_at(n_src, n_dst / n_src, origin, n_dst, dtype, src, dst, stream);
+    return interpolate_add_step(n_src, n_src / a, n_dst / a, origin, n_dst, dtype, src, dst, stream);
 }
 
 gg_status gg_lowpass(const gg_plan* pc, const void* field, int64_t n2_max, int32_t cic_deconvolve, void* out, void* work,

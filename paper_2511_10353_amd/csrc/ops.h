@@ -71,8 +71,8 @@ struct Ops {
     static hipError_t refine(int variant, const T* parent, int n_parent, const int origin[3], int count,
                              uint64_t seed, uint32_t stream_id, T* child, hipStream_t s);
     // dst (3 fields of n_dst^3) += cloud-in-cell interpolation of the periodic
-    // src (3 fields of n_src^3) at origin + m / ratio (src cells)
-    static hipError_t cic_add(const T* src, int n_src, int ratio, const int origin[3], T* dst, int n_dst,
+    // src (3 fields of n_src^3) at origin + m num / den (src cells)
+    static hipError_t cic_add(const T* src, int n_src, int num, int den, const int origin[3], T* dst, int n_dst,
                               hipStream_t s);
     // Eq. 5 on a real field: modes with n^2 >= n2_max dropped, optional CiC
     // deconvolution; out (R) may equal field; work: two plain half spectra

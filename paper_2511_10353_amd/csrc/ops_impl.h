@@ -448,15 +448,15 @@ hipError_t Ops<T>::refine(int variant, const T* parent, int n_parent, const int 
 }
 
 template <typename T>
-hipError_t Ops<T>::cic_add(const T* src, int n_src, int ratio, const int origin[3], T* dst, int n_dst,
+hipError_t Ops<T>::cic_add(const T* src, int n_src, int num, int den, const int origin[3], T* dst, int n_dst,
                            hipStream_t s) {
-    if (n_src < 1 || n_dst < 1 || ratio < 1) return hipErrorInvalidValue;
+    if (n_src < 1 || n_dst < 1 || num < 1 || den < 1) return hipErrorInvalidValue;
     for (int a = 0; a < 3; ++a)
         if (origin[a] < 0 || origin[a] >= n_src) return hipErrorInvalidValue;
     if (n_dst > 4096) return hipErrorInvalidValue;
     const unsigned bc = n_dst < 256 ? (unsigned)((n_dst + 63) / 64 * 64) : 256u;
     k_cic_add<T><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc), 3), bc, 0, s>>>(
-        src, n_src, ratio, origin[0], origin[1], origin[2], dst, n_dst);
+        src, n_src, num, den, origin[0], origin[1], origin[2], dst, n_dst);
     return hipGetLastError();
 }
 

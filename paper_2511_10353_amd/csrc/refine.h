@@ -206,12 +206,14 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
 }
 
 // dst (3 fields of nd^3) += trilinear interpolation of the periodic src (3
-// fields of ns^3) at the points u = o + m / R (src cells), m < nd per axis.
-// The weights are exact multiples of 1/R; products and sums in binary64, then
+// fields of ns^3) at the points u = o + m num / den (src cells), m < nd per
+// axis (num / den = 1 / R for a refinement by an integer R, n_src / n_dst in
+// lowest terms for a whole box resampled to another size).  Cell and weight
+// come from exact integer arithmetic; products and sums in binary64, then
 // rounded to T.
 template <typename T>
-__global__ void k_cic_add(const T* __restrict__ src, int ns, int R, int o0, int o1, int o2, T* __restrict__ dst,
-                          int nd) {
+__global__ void k_cic_add(const T* __restrict__ src, int ns, int num, int den, int o0, int o1, int o2,
+                          T* __restrict__ dst, int nd) {
     // block: one destination row (x, y) = blockIdx.x and a run of z; comp = blockIdx.z
     const int z = blockIdx.y * blockDim.x + threadIdx.x;
     if (z >= nd) return;
@@ -220,8 +222,10 @@ __global__ void k_cic_add(const T* __restrict__ src, int ns, int R, int o0, int 
     const uint64_t n3d = (uint64_t)nd * nd * nd;
     const uint64_t n3s = (uint64_t)ns * ns * ns;
     const int comp = blockIdx.z;
-    const int x0 = (o0 + x / R) % ns, y0 = (o1 + y / R) % ns, z0 = (o2 + z / R) % ns;
-    const double tx = (double)(x % R) / R, ty = (double)(y % R) / R, tz = (double)(z % R) / R;
+    // point m sits at o + m num / den source cells: cell o + floor(m num / den), weight (m num mod den) / den
+    const int xn = x * num, yn = y * num, zn = z * num;
+    const int x0 = (o0 + xn / den) % ns, y0 = (o1 + yn / den) % ns, z0 = (o2 + zn / den) % ns;
+    const double tx = (double)(xn % den) / den, ty = (double)(yn % den) / den, tz = (double)(zn % den) / den;
     const int x1 = x0 + 1 == ns ? 0 : x0 + 1, y1 = y0 + 1 == ns ? 0 : y0 + 1, z1 = z0 + 1 == ns ? 0 : z0 + 1;
     const T* s = src + comp * n3s;
     auto at = [&](int i, int j, int k) { return (double)s[((uint64_t)i * ns + j) * ns + k]; };

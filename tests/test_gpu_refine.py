@@ -112,3 +112,42 @@ def test_resolution_increase_against_oracle(dtype, n_p):
     # particles on the child lattice from the combined field
     pos, vel = child.zeldovich(psi)
     assert float(pos.min()) >= 0.0 and float(pos.max()) < box
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n_src,n_dst", [(16, 24), (64, 96), (10, 14)])
+def test_interpolate_add_any_size_against_oracle(dtype, n_src, n_dst):
+    src = np.stack([inputs.real_field(n_src, 60 + j, NPDT[dtype]) for j in range(3)])
+    base = np.stack([inputs.real_field(n_dst, 70 + j, NPDT[dtype]) for j in range(3)])
+    dst = torch.from_numpy(base.copy()).cuda()
+    gg.interpolate_add(torch.from_numpy(src).cuda(), dst)
+    got = dst.cpu().numpy()
+    want = base.astype(np.float64) + np.stack([oref.cic_resample(src[j].astype(np.float64), n_dst) for j in range(3)])
+    if dtype == "f64":
+        assert np.abs(got - want).max() < 1e-14
+    else:
+        assert int(ulp_diff_f32(got, want.astype(np.float32)).max()) <= 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_three_halves_resolution_increase_against_oracle(dtype):
+    # three-cell patches (Eq. A.15): 64^3 -> 96^3 over the same box
+    n_p = 64
+    box = 6.25 * n_p
+    parent = _plan(n_p, box, dtype)
+    child = _plan(96, box, dtype)
+    c = oracle_cosmo(parent.cosmo)
+    wp = parent.noise(42)
+    w_child, psi = gg.increase_resolution(parent, child, wp, "3", seed=7, stream_id=1)
+    wp64 = wp.cpu().numpy().astype(np.float64)
+    wc_want = oref.refine(wp64, "3", seed=7, stream=1)
+    wc = w_child.cpu().numpy().astype(np.float64)
+    assert np.abs(wc - wc_want).max() < (1e-14 if dtype == "f64" else 2e-7 * np.abs(wc_want).max())
+    want = oref.combine(wp64, wc, box, c, 2 * box / n_p)
+    got = psi.cpu().numpy()
+    for j in range(3):
+        err = rel_rms(got[j], want[j])
+        say(f"[increase 3/2] {dtype} 64->96 comp {j} rel rms {err:.3e}")
+        assert err < TOL[dtype]
+    pos, vel = child.zeldovich(psi)
+    assert float(pos.min()) >= 0.0 and float(pos.max()) < box

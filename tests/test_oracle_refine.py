@@ -177,3 +177,42 @@ def test_combine_keeps_parent_large_scales():
     sel = np.abs(lowp) > 1e-6 * np.abs(lowp).max()  # modes with k_0 = 0 vanish in psi_0
     rel = np.abs(lowc[sel] - lowp[sel]) / np.abs(lowp[sel])
     assert sel.sum() >= 8 and rel.max() < 0.01
+
+
+def test_cic_resample_reproduces_cell_linear_fields():
+    # trilinear interpolation is exact for a field linear in each source index
+    # inside the cells it interpolates (away from the periodic wrap)
+    n, n_out = 8, 12
+    m = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    f = 1.5 * m[0] - 0.25 * m[1] + 2.0 * m[2] + 0.75
+    out = refine.cic_resample(f, n_out)
+    u = np.arange(n_out) * n / n_out
+    uu = np.meshgrid(u, u, u, indexing="ij")
+    want = 1.5 * uu[0] - 0.25 * uu[1] + 2.0 * uu[2] + 0.75
+    inner = u <= n - 1
+    sel = np.ix_(inner, inner, inner)
+    assert np.abs(out[sel] - want[sel]).max() < 1e-13
+
+
+def test_cic_resample_hits_source_points_and_matches_integer_upsampling():
+    f = inputs.real_field(8, 13)
+    out = refine.cic_resample(f, 12)
+    # output points 0, 3, 6, 9 sit on source points 0, 2, 4, 6 (u = 2m/3)
+    assert np.array_equal(out[::3, ::3, ::3], f[::2, ::2, ::2])
+    a = refine.cic_resample(f, 16)
+    b = refine.cic_upsample(f, 2)
+    assert np.abs(a - b).max() <= 2 * np.spacing(np.abs(b).max())
+
+
+def test_three_halves_combine_whole_box_limit():
+    # the 3/2 resolution increase: with r_s so small that Eq. 4 keeps nothing
+    # below the child Nyquist the result is the CiC-resampled parent field
+    n_p = 16
+    box = 40.0
+    wp = noise.noise_grid(n_p, 2)
+    wc = refine.refine(wp, "3", seed=4, stream=1)
+    assert wc.shape == (24, 24, 24)
+    r_s = box  # k r_s < 1 keeps only k = 0 in the large part, Eq. 4 keeps everything else
+    psi = refine.combine(wp, wc, box, COSMO, r_s)
+    full = np.stack(pipeline.displacement_fields(wc, 24, box, COSMO))
+    assert np.abs(psi - full).max() < 1e-13 * np.abs(full).max()
