@@ -45,6 +45,11 @@
  * - Arguments are validated before anything is launched: a bad argument
  *   returns GG_ERR_INVALID_ARG and launches nothing.  gg_last_error() then
  *   holds a message (per thread).  No call throws across the ABI.
+ * - Failure injection for tests: with the environment variable
+ *   GG_FAULT_INJECT=plan_alloc, gg_plan_create fails its last device
+ *   allocation (GG_ERR_OUT_OF_MEMORY, the earlier ones freed); with
+ *   GG_FAULT_INJECT=launch, gg_make_ic returns GG_ERR_HIP without launching.
+ *   The variable is read on each call; unset, it changes nothing.
  * - A plan is read-only after gg_plan_create, except for the timing records
  *   of gg_timing_enable.  gg_noise, gg_fft3d, gg_filter and gg_zeldovich on one
  *   plan may run from several streams (each with its own buffers);

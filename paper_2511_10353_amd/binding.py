@@ -15,6 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GG_LIBRARY") or os.path.join(_PKG, "libgg.so")
 
 GG_OK = 0
+GG_ERR_INVALID_ARG, GG_ERR_UNSUPPORTED_SIZE, GG_ERR_OUT_OF_MEMORY, GG_ERR_HIP, GG_ERR_INTERNAL = 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "GG_OK", 1: "GG_ERR_INVALID_ARG", 2: "GG_ERR_UNSUPPORTED_SIZE",
                 3: "GG_ERR_OUT_OF_MEMORY", 4: "GG_ERR_HIP", 5: "GG_ERR_INTERNAL"}
 DTYPES = {"f32": 0, "f64": 1}

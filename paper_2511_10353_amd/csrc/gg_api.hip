@@ -71,6 +71,14 @@ namespace {
 
 bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
+// Test hook: GG_FAULT_INJECT names one failure to simulate ("plan_alloc": the
+// last device allocation of gg_plan_create fails; "launch": gg_make_ic
+// reports a failed launch without launching).  Unset, it changes nothing.
+bool fault_injected(const char* point) {
+    const char* v = std::getenv("GG_FAULT_INJECT");
+    return v && std::strcmp(v, point) == 0;
+}
+
 template <typename T>
 gg::PlanView<T> view(const gg_plan* p) {
     gg::PlanView<T> v;
@@ -204,8 +212,10 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     do {
         if ((e = hipMalloc(&p->tw, 2 * es * p->n)) != hipSuccess ||
             (e = hipMalloc(&p->tau, es * p->ntau)) != hipSuccess || (e = hipMalloc(&d_sig, sizeof(double))) != hipSuccess ||
-            (e = hipMalloc(&p->tauseg, dtype == GG_F32 ? gg::kTauSeg * sizeof(float4)
-                                                       : gg::kTauSeg64 * (gg::kTauDeg64 + 1) * sizeof(double))) !=
+            (e = fault_injected("plan_alloc")
+                     ? hipErrorOutOfMemory
+                     : hipMalloc(&p->tauseg, dtype == GG_F32 ? gg::kTauSeg * sizeof(float4)
+                                                             : gg::kTauSeg64 * (gg::kTauDeg64 + 1) * sizeof(double))) !=
                 hipSuccess) {
             st = fail(GG_ERR_OUT_OF_MEMORY, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
             break;
@@ -451,7 +461,9 @@ gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, v
         p->recorded++;
     }
     hipError_t e;
-    if (p->dtype == GG_F64)
+    if (fault_injected("launch"))
+        e = hipErrorLaunchFailure;
+    else if (p->dtype == GG_F64)
         e = gg::Ops<double>::make_ic(view<double>(p), seed, pos, vel, static_cast<double*>(psi_opt),
                                      static_cast<gg::cx<double>*>(work), x);
     else
