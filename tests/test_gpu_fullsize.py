@@ -45,6 +45,24 @@ def test_float_noise_is_rounded_double_noise_at_1024():
     torch.cuda.empty_cache()
 
 
+def test_launch_configurations_agree_bitwise_at_1024():
+    # the benchmark's autotuned configuration (one chunk, 8-line first pass,
+    # 16-line last pass) against the built-in one and a pipelined one
+    p = gg.Plan(N, BOX, gg.Cosmo(), dtype="f32")
+    ref = p.make_ic(SEED)
+    torch.cuda.synchronize()
+    for tuning in ((1, 8, 16), (4, 16, 8)):
+        say(f"[1024] make_ic at tuning {tuning}")
+        p.set_tuning(*tuning)
+        got = p.make_ic(SEED)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), tuning
+        del got
+    del ref
+    p.close()
+    torch.cuda.empty_cache()
+
+
 def test_fp32_matches_fp64_at_1024():
     say(f"[1024] FP64 make_ic")
     p64 = gg.Plan(N, BOX, gg.Cosmo(), dtype="f64")
