@@ -233,13 +233,55 @@ __device__ __forceinline__ int last_pos(int j, int i) {
 template <int L>
 __device__ __forceinline__ int lidx(int row, int col) { return row * L + (col ^ (row & (L - 1))); }
 
+// The 1024-point plan (16, 4, 16) with 64 threads per line: the exchange
+// between the radix-4 stage and the last radix-16 stage sends the outputs of
+// thread j only to the threads j % 16 + 16 r, r < 4.  Placing thread j of a
+// line in 16-lane row j / 16 of a wave (float tiles, 16 lines: wave j % 16,
+// lane 16 (j / 16) + column; double tiles, 8 lines: wave (j % 16) / 2, lane
+// 16 (j / 16) + 8 (j % 2) + column) puts those four threads in the four rows
+// of one wave at the same position within the row, so the exchange is a 4 x 4
+// transpose across rows, two lane swaps per 32-bit register
+// (v_permlane32_swap, then v_permlane16_swap), instead of an LDS round trip
+// and a work-group barrier.
+template <typename T, int M, int L>
+struct RowExchange {
+    static constexpr bool value = M == 1024 && PlanInfo<M>::TPL == 64 && Plan<M>::S == 3 && Plan<M>::R[0] == 16 &&
+                                  Plan<M>::R[1] == 4 && Plan<M>::R[2] == 16 &&
+                                  ((sizeof(T) == 4 && L == 16) || (sizeof(T) == 8 && L == 8));
+};
+
+// Line-local thread index j of work-group thread t (the column is t % L);
+// RX: the row-exchange placement above.
+template <bool RX, int L>
+__device__ __forceinline__ int line_thread(int t) {
+    if constexpr (RX && L == 16) return (t >> 6) + 16 * ((t & 63) >> 4);
+    else if constexpr (RX && L == 8) return 2 * (t >> 6) + ((t >> 3) & 1) + 16 * ((t & 63) >> 4);
+    else return t / L;
+}
+
+// x_r <- x of row r (16-lane rows of the wave) held in the caller's register
+// q = own row: a 4 x 4 transpose of four registers across the four rows.
+__device__ __forceinline__ void row_transpose4(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3) {
+    const auto a = __builtin_amdgcn_permlane32_swap(x0, x2, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(x1, x3, false, false);
+    const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+    const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+    x0 = c[0];
+    x1 = c[1];
+    x2 = d[0];
+    x3 = d[1];
+}
+
 // One Stockham stage (see the file header).  tw[m * TWS] = exp(-2 pi i m / M).
-template <typename T, int M, int L, int R, int NS, int DIR, int TWS, bool FIRST, bool LAST>
+// RIN: the stage's inputs are already in registers (after a row exchange);
+// ROUT: the outputs go to the next stage by the row exchange, not LDS.
+template <typename T, int M, int L, int R, int NS, int DIR, int TWS, bool FIRST, bool LAST, bool RIN = false,
+          bool ROUT = false>
 __device__ __forceinline__ void stockham_stage(cx<T>* v, cx<T>* lds, const cx<T>* __restrict__ tw, int c, int j) {
     constexpr int TPL = PlanInfo<M>::TPL;
     constexpr int BPT = PlanInfo<M>::RMAX / R;
     constexpr int NB = M / R;
-    if constexpr (!FIRST) {
+    if constexpr (!FIRST && !RIN) {
 #pragma unroll
         for (int u = 0; u < BPT; ++u)
 #pragma unroll
@@ -258,22 +300,54 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, cx<T>* lds, const cx<T>
             }
         }
         dft<R, DIR>(v + u * R);
-        if constexpr (!LAST) {
+        if constexpr (ROUT) {
+            // output r of this thread's butterfly u goes to row r of the wave, slot
+            // 4 u + (own row): transpose the four outputs across the rows
+            static_assert(R == 4, "row exchange is a 4 x 4 transpose");
+            constexpr int W = sizeof(T) / 4;  // 32-bit words per component
+            uint32_t re[W][4], im[W][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                __builtin_memcpy(&re[0][r], &v[u * R + r].x, 4);
+                __builtin_memcpy(&im[0][r], &v[u * R + r].y, 4);
+                if constexpr (W == 2) {
+                    __builtin_memcpy(&re[1][r], reinterpret_cast<const char*>(&v[u * R + r].x) + 4, 4);
+                    __builtin_memcpy(&im[1][r], reinterpret_cast<const char*>(&v[u * R + r].y) + 4, 4);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < W; ++h) {
+                row_transpose4(re[h][0], re[h][1], re[h][2], re[h][3]);
+                row_transpose4(im[h][0], im[h][1], im[h][2], im[h][3]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                __builtin_memcpy(&v[u * R + r].x, &re[0][r], 4);
+                __builtin_memcpy(&v[u * R + r].y, &im[0][r], 4);
+                if constexpr (W == 2) {
+                    __builtin_memcpy(reinterpret_cast<char*>(&v[u * R + r].x) + 4, &re[1][r], 4);
+                    __builtin_memcpy(reinterpret_cast<char*>(&v[u * R + r].y) + 4, &im[1][r], 4);
+                }
+            }
+        } else if constexpr (!LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) lds[lidx<L>((b - k) * R + k + r * NS, c)] = v[u * R + r];
         }
     }
-    if constexpr (!LAST) __syncthreads();
+    if constexpr (!LAST && !ROUT) __syncthreads();
 }
 
 // Full transform of one line per column: inputs in v at first_pos, outputs
-// in v at last_pos.  On return every thread has finished with LDS.
-template <typename T, int M, int L, int DIR, int TWS, int s = 0, int NS = 1>
+// in v at last_pos.  On return every thread has finished with LDS.  RX: the
+// exchange before the last stage runs across the rows of each wave (threads
+// placed by line_thread<true>); only for plans with RowExchange.
+template <typename T, int M, int L, int DIR, int TWS, bool RX = false, int s = 0, int NS = 1>
 __device__ __forceinline__ void fft_lines(cx<T>* v, cx<T>* lds, const cx<T>* __restrict__ tw, int c, int j) {
+    static_assert(!RX || RowExchange<T, M, L>::value, "row exchange needs the (16, 4, 16) float plan");
     constexpr int S = Plan<M>::S;
     constexpr int R = (DIR < 0) ? Plan<M>::R[s] : Plan<M>::R[S - 1 - s];
-    stockham_stage<T, M, L, R, NS, DIR, TWS, (s == 0), (s == S - 1)>(v, lds, tw, c, j);
-    if constexpr (s + 1 < S) fft_lines<T, M, L, DIR, TWS, s + 1, NS * R>(v, lds, tw, c, j);
+    stockham_stage<T, M, L, R, NS, DIR, TWS, (s == 0), (s == S - 1), RX && s == 2, RX && s == 1>(v, lds, tw, c, j);
+    if constexpr (s + 1 < S) fft_lines<T, M, L, DIR, TWS, RX, s + 1, NS * R>(v, lds, tw, c, j);
 }
 
 // Lines per work-group: one 128-byte LDS row of complex values.

@@ -495,7 +495,11 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
                   "inverse plan must start where the forward plan ends");
     __shared__ cx<T> lds[L * N];
     const int t = threadIdx.x;
-    const int c = t % L, j = t / L;
+    // y-passes (plain row strides) exchange the last stage across wave rows;
+    // the x-passes keep the consecutive-row placement, whose four rows per
+    // wave instruction sit in one blocked 8-row group
+    constexpr bool RX = RowExchange<T, N, L>::value && !PBLK;
+    const int c = t % L, j = line_thread<RX, L>(t);
     const int o = a.o0 + (int)(blockIdx.x / a.ncb);
     const int col0 = (a.cb0 + (int)(blockIdx.x % a.ncb)) * L;
     const int col = col0 + c;
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         const uint32_t lb = lane_bytes(j);
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RI, j, lb);
-        fft_lines<T, N, L, DIR, 1>(v, lds, pv.tw, c, j);
+        fft_lines<T, N, L, DIR, 1, RX>(v, lds, pv.tw, c, j);
         if (valid) {
 #pragma unroll
             for (int i = 0; i < V; ++i) *at(a.out0, i, RO, j, lb) = v[i];
@@ -551,7 +555,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
         __syncthreads();
-        fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, c, j);
+        fft_lines<T, N, L, -1, 1, RX>(v, lds, pv.tw, c, j);
         // Eq. (1)-(2) on the spectrum held in registers (positions = axis-0 modes)
         const int s1 = signed_mode(o, N);
         const int s2 = col;
@@ -571,7 +575,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         }
         {
             const int jj = opaque(j), cc = opaque(c);
-            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+            fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);
             const uint32_t lb2 = lane_bytes(jj);
             if (valid) {
 #pragma unroll
@@ -580,7 +584,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         }
         {
             const int jj = opaque(j), cc = opaque(c);
-            fft_lines<T, N, L, 1, 1>(g, lds, pv.tw, cc, jj);
+            fft_lines<T, N, L, 1, 1, RX>(g, lds, pv.tw, cc, jj);
             const uint32_t lb2 = lane_bytes(jj);
             if (valid) {
 #pragma unroll
@@ -603,7 +607,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             const cx<T>* src = comp == 0 ? a.in0 : (comp == 1 ? a.in1 : a.in2);
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = *at(src, i, RF, jj, lb);
-            fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, cc, jj);
+            fft_lines<T, N, L, -1, 1, RX>(v, lds, pv.tw, cc, jj);
             const int jk = opaque(jj);
             const T sc = (T)(comp == 1 ? s1 : s2);
 #pragma unroll
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
                 const T tau = taul(zero ? 0 : n2) * (T)pv.amp_scale;
                 v[i] = mul_i(cscale(acc[i], -tau));
             }
-            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+            fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);
             const uint32_t lb = lane_bytes(jj);
             if (valid) {
 #pragma unroll
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
         __syncthreads();
-        fft_lines<T, N, L, -1, 1>(v, lds, pv.tw, c, j);
+        fft_lines<T, N, L, -1, 1, RX>(v, lds, pv.tw, c, j);
         const int s1 = signed_mode(o, N);
         const int s2 = col;
         const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
@@ -653,7 +657,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             if (pv.deconv) f *= cic_deconv<T>(s0, N) * dline;
             v[i] = cscale(v[i], f);
         }
-        fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+        fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);
         const uint32_t lb2 = lane_bytes(jj);
         if (valid) {
 #pragma unroll
@@ -664,7 +668,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             const uint32_t lb = lane_bytes(j);
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RM, j, lb);
-            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, c, j);
+            fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, c, j);
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out0, i, RL, j, lb) = v[i];
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
                 g[i] = *at(a.in1, i, RM, jj, lb);
                 v[i] = cscale(g[i], (T)signed_mode(first_pos<N, 1>(jj, i), N));
             }
-            fft_lines<T, N, L, 1, 1>(v, lds, pv.tw, cc, jj);
+            fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out1, i, RL, jj, lb) = v[i];
@@ -688,7 +692,7 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         {
             const int jj = opaque(j), cc = opaque(c);
             const uint32_t lb = lane_bytes(jj);
-            fft_lines<T, N, L, 1, 1>(g, lds, pv.tw, cc, jj);
+            fft_lines<T, N, L, 1, 1, RX>(g, lds, pv.tw, cc, jj);
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out2, i, RL, jj, lb) = g[i];
