@@ -45,6 +45,38 @@ def test_float_noise_is_rounded_double_noise_at_1024():
     torch.cuda.empty_cache()
 
 
+def test_plain_transforms_at_1024():
+    # the stand-alone r2c / c2r at 1024^3 (its axis-1 passes exchange inside
+    # waves; the 513-column half spectrum ends in a ragged tile): sampled modes
+    # against direct sums in float64 and the round trip over the whole field
+    x = inputs.real_field(N, 31, np.float32)
+    p = gg.Plan(N, BOX, gg.Cosmo(), dtype="f32")
+    xd = torch.from_numpy(x).cuda()
+    spec = p.fft3d(xd, 1)
+    torch.cuda.synchronize()
+    modes = [(0, 0, 0), (1, 2, 3), (1023, 511, 512), (512, 17, 256), (300, 1000, 511)]
+    got = [complex(spec[k].item()) for k in modes]
+    xf = x.reshape(N * N, N).astype(np.float64)
+    m = np.arange(N)
+    for k, g in zip(modes, got):
+        e = [np.exp(-2j * np.pi * kk * m / N) for kk in k]
+        t2 = xf @ e[2].real + 1j * (xf @ e[2].imag)  # axis 2 (real matrix, no complex copy of it)
+        t1 = t2.reshape(N, N) @ e[1]         # axis 1
+        want = t1 @ e[0]                     # axis 0
+        rms = np.sqrt(N ** 3)                # |X| scale of unit white noise
+        say(f"[1024 fft] mode {k}: |got - want| / sqrt(N^3) = {abs(g - want) / rms:.3e}")
+        assert abs(g - want) < 2e-5 * rms
+    del xf
+    y = p.fft3d(spec, -1)
+    torch.cuda.synchronize()
+    err = _rel_rms_t(y, xd)
+    say(f"[1024 fft] round trip rel rms {err:.3e}")
+    assert err < 1e-6
+    del spec, y, xd
+    p.close()
+    torch.cuda.empty_cache()
+
+
 def test_launch_configurations_agree_bitwise_at_1024():
     # the benchmark's autotuned configuration (one chunk, 8-line first pass,
     # 16-line last pass) against the built-in one and a pipelined one
