@@ -169,6 +169,44 @@ def time_zoom(gg, torch, steps, seed=42):
     return out
 
 
+def time_extras(gg, torch, reps=5, n=1024, box=2000.0):
+    """The other outputs at the measured size, FP32: the density field (Eq. 1)
+    and its binned P(k) at n^3, the full-box resolution increase (n/2)^3 -> n^3
+    (4-cell patches of App. A, Eq. 4-5 with CiC) and the degrade n^3 ->
+    (n/2)^3 of one field (NGP + half-cell Fourier shift)."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    p = gg.Plan(n, box, gg.Cosmo(), dtype="f32")
+    parent = gg.Plan(n // 2, box, gg.Cosmo(), dtype="f32")
+    work = p.workspace()
+    delta = p.make_density(42, work=work)
+    out = {"workload": f"{n}^3 / {box:g} Mpc/h, FP32", "reps": reps}
+    ms = timed(lambda: p.make_density(42, out=delta, work=work))
+    out["density"] = {"ms": round(ms, 4), "cells_per_s": round(n ** 3 / (ms * 1e-3), 1)}
+    ms = timed(lambda: p.power_spectrum(delta, n // 2, work=work))
+    out["power_spectrum"] = {"ms": round(ms, 4), "bins": n // 2}
+    wp = parent.noise(42)
+    ms = timed(lambda: gg.increase_resolution(parent, p, wp, "4", seed=7, stream_id=1))
+    out["increase_resolution"] = {"ms": round(ms, 4), "from": n // 2, "to": n,
+                                  "child_cells_per_s": round(n ** 3 / (ms * 1e-3), 1)}
+    small = parent.workspace()
+    ms = timed(lambda: parent.degrade(delta, 2, work=small))
+    out["degrade"] = {"ms": round(ms, 4), "from": n, "to": n // 2, "fields": 1}
+    del p, parent, work, small, delta, wp
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_bytes(n, elem, log_amp):
     """Algorithmic HBM bytes of the adjoint's passes A1-A5 for a gradient given
     with respect to the displacements only."""
@@ -293,6 +331,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-zoom", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the density / P(k) / refinement / degrade timings")
     ap.add_argument("--tuning", default=None, metavar="CHUNKS,P1_LINES,Z_LINES",
                     help="fixed launch configuration of the FP32 path instead of the autotuner "
                          "(the FP64 path then keeps its built-in one)")
@@ -365,6 +404,8 @@ def main():
         out["zoom"] = time_zoom(gg, torch, max(args.steps // 2, 1))
     if not args.no_adjoint:
         out["adjoint"] = time_adjoint(gg, torch, args.n, args.box, "f32", max(args.steps // 2, 1), 1)
+    if not args.no_extras and args.n >= 16:
+        out["extras"] = time_extras(gg, torch, n=args.n, box=args.box)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
