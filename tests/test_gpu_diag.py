@@ -74,7 +74,7 @@ def test_density_is_minus_divergence_of_displacements():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("n,nbins", [(8, 8), (32, 28), (128, 100)])
+@pytest.mark.parametrize("n,nbins", [(8, 8), (32, 28), (128, 100), (64, 1024), (256, 200)])
 def test_power_spectrum_against_oracle(dtype, n, nbins):
     box = 7.0 * n
     p = _plan(n, box, dtype)
@@ -83,7 +83,8 @@ def test_power_spectrum_against_oracle(dtype, n, nbins):
     wpk, wkm, wct = ostats.power_spectrum(f.astype(np.float64), box, nbins)
     assert np.array_equal(ct, wct)
     nz = wct > 0
-    assert np.abs(km[nz] / wkm[nz] - 1).max() < 1e-13
+    # binary64 sums of up to ~10^7 terms per bin, in another order than numpy's
+    assert np.abs(km[nz] / wkm[nz] - 1).max() < 1e-12
     rel = np.abs(pk[nz] / wpk[nz] - 1)
     say(f"[pk] n={n} {dtype} max rel {rel.max():.3e}")
     assert rel.max() < TOL[dtype]
