@@ -64,6 +64,36 @@ def test_transfer_limits():
     assert np.all(np.diff(t) < 0) and np.all(t > 0)
 
 
+def test_transfer_series_at_small_q():
+    # Taylor coefficients of T(q) = L(q) G(q) derived by hand:
+    # L = ln(1 + a q)/(a q) = 1 - a q/2 + (a q)^2/3 - (a q)^3/4 + ...,
+    # G = (1 + x)^(-1/4) = 1 - x/4 + 5 x^2/32 - 15 x^3/128 + ... with
+    # x = b1 q + b2 q^2 + b3 q^3 + b4 q^4.  Each of the first three orders
+    # brings in one more coefficient of the fit (a and b1, then b2, then b3).
+    a, b1, b2, b3 = 2.34, 3.89, 16.1 ** 2, 5.46 ** 3
+    l1, l2, l3 = -a / 2, a * a / 3, -a ** 3 / 4
+    g1 = -b1 / 4
+    g2 = -b2 / 4 + 5 * b1 ** 2 / 32
+    g3 = -b3 / 4 + 5 * b1 * b2 / 16 - 15 * b1 ** 3 / 128
+    want = [1.0, l1 + g1, l2 + l1 * g1 + g2, l3 + l2 * g1 + l1 * g2 + g3]
+    gamma, qmax = 0.21, 0.005
+    q = np.linspace(qmax / 400, qmax, 400)
+    t = cosmology.bbks_transfer(q * gamma, gamma)
+    got = np.polynomial.Polynomial.fit(q, t, 10, domain=[-qmax, qmax]).convert().coef
+    for order, tol in enumerate((1e-13, 1e-9, 1e-7, 1e-5)):
+        assert abs(got[order] / want[order] - 1.0) < tol, order
+
+
+def test_transfer_large_q_asymptote():
+    # for q -> infinity the bracket tends to (6.71 q)^4 and ln(1 + a q) to
+    # ln(a q): T q^2 6.71 a / ln(a q) -> 1, with corrections of order
+    # 1/(q ln q)
+    a, gamma = 2.34, 0.21
+    for q, tol in ((1e6, 2e-8), (1e8, 1e-10)):
+        t = cosmology.bbks_transfer(np.array([q * gamma]), gamma)[0]
+        assert abs(t * 6.71 * a * q * q / np.log(a * q) - 1.0) < tol
+
+
 def test_window_series_joins_closed_form():
     x = np.array([0.00999999, 0.01000001])
     w = cosmology.tophat_window(x)
