@@ -57,6 +57,8 @@ struct gg_plan {
     // tile choices of the fused path (0 = built-in; set by gg_plan_set_tuning
     // or gg_plan_autotune)
     int p1_lines = 0, z_lines = 0;
+    // work-groups of the last pass (16 per compute unit of the plan's device)
+    int zel_blocks = 0;
     // pipelined launch of the fused path: auxiliary stream, dependency events
     int nchunk = 1;
     hipStream_t aux = nullptr;
@@ -70,6 +72,19 @@ struct gg_plan {
 namespace {
 
 bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+// launch context of the fused path for plan p on the caller's stream
+gg::ExecCtx fused_ctx(gg_plan* p, void* stream) {
+    gg::ExecCtx x;
+    x.a = static_cast<hipStream_t>(stream);
+    x.b = p->aux;
+    x.sync = p->sync.empty() ? nullptr : p->sync.data();
+    x.nchunk = p->nchunk;
+    x.p1_lines = p->p1_lines;
+    x.z_lines = p->z_lines;
+    x.zel_blocks = p->zel_blocks;
+    return x;
+}
 
 // Test hook: GG_FAULT_INJECT names one failure to simulate ("plan_alloc": the
 // last device allocation of gg_plan_create fails; "launch": gg_make_ic
@@ -195,10 +210,13 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     p->cosmo = c;
     p->cell = grid->box / (double)grid->n;
     hipError_t e = hipGetDevice(&p->device);
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) {
         delete p;
-        return fail_hip(e, "hipGetDevice");
+        return fail_hip(e, "hipGetDevice / compute unit count");
     }
+    p->zel_blocks = 16 * (cus > 0 ? cus : 256);
     const size_t es = elem_size(dtype);
     const int half = p->n / 2;
     p->ntau = 3LL * half * half + 1;
@@ -449,13 +467,7 @@ gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, v
     gg_status st = check_device(pc);
     if (st != GG_OK) return st;
     gg_plan* p = const_cast<gg_plan*>(pc);  // timing records are the plan's only mutable state
-    gg::ExecCtx x;
-    x.a = static_cast<hipStream_t>(stream);
-    x.b = p->aux;
-    x.sync = p->sync.empty() ? nullptr : p->sync.data();
-    x.nchunk = p->nchunk;
-    x.p1_lines = p->p1_lines;
-    x.z_lines = p->z_lines;
+    gg::ExecCtx x = fused_ctx(p, stream);
     if (p->timing && p->recorded < kTimingSlots) {
         x.tev = &p->events[(size_t)p->recorded * 2 * kLaunchesMax];
         p->recorded++;
@@ -491,13 +503,7 @@ gg_status gg_make_ic_from_noise(const gg_plan* pc, const void* w, double amp_sca
     gg_status st = check_device(pc);
     if (st != GG_OK) return st;
     gg_plan* p = const_cast<gg_plan*>(pc);
-    gg::ExecCtx x;
-    x.a = static_cast<hipStream_t>(stream);
-    x.b = p->aux;
-    x.sync = p->sync.empty() ? nullptr : p->sync.data();
-    x.nchunk = p->nchunk;
-    x.p1_lines = p->p1_lines;
-    x.z_lines = p->z_lines;
+    gg::ExecCtx x = fused_ctx(p, stream);
     hipError_t e;
     if (p->dtype == GG_F64) {
         auto v = view<double>(p);
@@ -676,13 +682,7 @@ gg_status gg_make_displacements(const gg_plan* pc, const void* w, int64_t n2_min
     const int lo = (int)(n2_min < big ? n2_min : big);
     const int hi = (int)(n2_max <= 0 || n2_max > big ? big : n2_max);
     gg_plan* p = const_cast<gg_plan*>(pc);
-    gg::ExecCtx x;
-    x.a = static_cast<hipStream_t>(stream);
-    x.b = p->aux;
-    x.sync = p->sync.empty() ? nullptr : p->sync.data();
-    x.nchunk = p->nchunk;
-    x.p1_lines = p->p1_lines;
-    x.z_lines = p->z_lines;
+    gg::ExecCtx x = fused_ctx(p, stream);
     hipError_t e;
     if (p->dtype == GG_F64) {
         auto v = view<double>(p);

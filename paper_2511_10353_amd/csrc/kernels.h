@@ -339,24 +339,31 @@ __device__ __forceinline__ void zel_point(T psi, int m, double origin, double ce
 }
 
 // ---------------------------------------------------------------------------
-// P5 / inverse axis-2 pass: L half-spectrum lines -> real lines.  With the
-// packing above run backwards: Z[k] = (X[k] + conj X[M-k]) +
-// i W_N^-k (X[k] - conj X[M-k]) (Z[0] from the real parts of X[0], X[M]),
-// an M-point inverse gives x[2m] + i x[2m+1] (unnormalised).
-// MODE 0: write scale * x to a real field (plain rows).  MODE 1: Eq. (3) for
-// component blockIdx.y, whose spectrum is multiplied by s_2 = k for
-// component 2 (rows as given by BLK).
+// Inverse axis-2 pass: L half-spectrum lines -> real lines.  With the packing
+// above run backwards: Z[k] = (X[k] + conj X[M-k]) + i W_N^-k (X[k] - conj
+// X[M-k]) (Z[0] from the real parts of X[0], X[M]), an M-point inverse gives
+// x[2m] + i x[2m+1] (unnormalised).  Writes scale * x to a real field (plain
+// rows); the input rows are plain or blocked as BLK says.
 // ---------------------------------------------------------------------------
-struct ZelArgs {
-    float* pos;
-    float* vel;
-    void* psi;  // optional displacement output (path type), may be null
-};
 
-template <typename T, int N, int MODE, bool BLK, int L = Tile<T>::L>
-__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
-    const cx<T>* __restrict__ in0, const cx<T>* __restrict__ in1, const cx<T>* __restrict__ in2, int istride,
-    T* __restrict__ out, T scale, PlanView<T> pv, ZelArgs za) {
+// Z[p] of the packing from the LDS tile (X[M] of every line is nyq[c]).
+template <typename T, int M, int L>
+__device__ __forceinline__ cx<T> c2r_pack(const cx<T>* lds, const cx<T>* tw, T nyq, int p, int c) {
+    const cx<T> xp = lds[lidx<L>(p, c)];
+    if (p == 0) {
+        const T a0 = xp.x;
+        return {a0 + nyq, a0 - nyq};
+    }
+    const cx<T> xm = lds[lidx<L>(M - p, c)];
+    const cx<T> b = {xm.x, -xm.y};
+    const cx<T> s = cadd(xp, b);
+    const cx<T> d = csub(xp, b);
+    return cadd(s, mul_i(cmulc(d, tw[p])));
+}
+
+template <typename T, int N, bool BLK, int L = Tile<T>::L>
+__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(const cx<T>* __restrict__ in, int istride,
+                                                                   T* __restrict__ out, T scale, PlanView<T> pv) {
     constexpr int M = N / 2;
     constexpr int TPL = PlanInfo<M>::TPL;
     constexpr int NT = L * TPL;
@@ -366,82 +373,150 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(
     const int t = threadIdx.x;
     const int c = t % L, j = t / L;
     const uint64_t line0 = (uint64_t)blockIdx.x * L;
-    const int comp = (MODE == 1) ? (int)blockIdx.y : 0;
-    const cx<T>* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
-    const bool zmul = (MODE == 1) && comp == 2;
     const cx<T>* src = in + line0 * istride;
     if (istride == M) {
         for (int fi = t; fi < L * M / 2; fi += NT) {
             const int cc = fi / (M / 2), k = 2 * (fi % (M / 2));
-            cx<T> x0 = src[2 * fi], x1 = src[2 * fi + 1];
-            if (zmul) {
-                x0 = cscale(x0, (T)k);
-                x1 = cscale(x1, (T)(k + 1));
-            }
-            lds[lidx<L>(k, cc)] = x0;
-            lds[lidx<L>(k + 1, cc)] = x1;
+            lds[lidx<L>(k, cc)] = src[2 * fi];
+            lds[lidx<L>(k + 1, cc)] = src[2 * fi + 1];
         }
         if (t < L) nyq[t] = (T)0;
     } else {
         for (int fi = t; fi < L * M; fi += NT) {
             const int cc = fi / M, k = fi % M;
-            cx<T> x = src[(int64_t)cc * istride + k];
-            if (zmul) x = cscale(x, (T)k);
-            lds[lidx<L>(k, cc)] = x;
+            lds[lidx<L>(k, cc)] = src[(int64_t)cc * istride + k];
         }
         if (t < L) nyq[t] = src[(int64_t)t * istride + M].x;
     }
     __syncthreads();
     cx<T> v[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-        const int p = first_pos<M, 1>(j, i);
-        const cx<T> xp = lds[lidx<L>(p, c)];
-        if (p == 0) {
-            const T a0 = xp.x, am = nyq[c];
-            v[i] = {a0 + am, a0 - am};
-        } else {
-            const cx<T> xm = lds[lidx<L>(M - p, c)];
-            const cx<T> b = {xm.x, -xm.y};
-            const cx<T> s = cadd(xp, b);
-            const cx<T> d = csub(xp, b);
-            v[i] = cadd(s, mul_i(cmulc(d, pv.tw[p])));
-        }
-    }
+    for (int i = 0; i < V; ++i) v[i] = c2r_pack<T, M, L>(lds, pv.tw, nyq[c], first_pos<M, 1>(j, i), c);
     __syncthreads();
     fft_lines<T, M, L, 1, 2>(v, lds, pv.tw, c, j);
 #pragma unroll
     for (int i = 0; i < V; ++i) lds[lidx<L>(last_pos<M, 1>(j, i), c)] = v[i];
     __syncthreads();
-    const uint64_t n3 = (uint64_t)N * N * N;
     // four consecutive reals (two complex slots) per lane
     for (int fi = t; fi < L * M / 2; fi += NT) {
         const int cc = fi / (M / 2), m = 2 * (fi % (M / 2));
         const cx<T> z0 = lds[lidx<L>(m, cc)], z1 = lds[lidx<L>(m + 1, cc)];
         int m0, m1;
         row_coords<BLK>(line0 + cc, N, m0, m1);
-        const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * m;
-        if constexpr (MODE == 0) {
-            T* o = out + cell;
-            *reinterpret_cast<cx<T>*>(o) = {z0.x * scale, z0.y * scale};
-            *reinterpret_cast<cx<T>*>(o + 2) = {z1.x * scale, z1.y * scale};
-        } else {
-            const uint64_t off = (uint64_t)comp * n3 + cell;
-            const T vals[4] = {z0.x, z0.y, z1.x, z1.y};
-            float p[4], u[4];
+        T* o = out + ((uint64_t)m0 * N + m1) * N + 2 * m;
+        *reinterpret_cast<cx<T>*>(o) = {z0.x * scale, z0.y * scale};
+        *reinterpret_cast<cx<T>*>(o + 2) = {z1.x * scale, z1.y * scale};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P5: the inverse axis-2 pass of the three displacement spectra (blocked rows,
+// k2 < M; the Nyquist plane is zero) fused with Eq. (3).  A tile is L lines
+// of one component; component 2's spectrum is multiplied by s_2 = k on the
+// way into LDS (its tau carries no s_2).  PV: write positions and
+// velocities; PS: write the displacements in the path's type.
+//
+// The grid is smaller than the tile count: work-group b takes tiles b, b + G,
+// b + 2G, ... (G = gridDim.x).  As soon as a tile sits in LDS, each thread
+// loads its share of the next tile into registers, so those HBM reads run
+// under the current tile's transform and stores.  The N-point twiddle table
+// is copied into LDS once per work-group, so that the loop issues no other
+// global load (loads complete in order: waiting for a later one would wait
+// for the prefetch too).  The prefetch after the last tile re-reads that
+// tile.
+// ---------------------------------------------------------------------------
+struct ZelArgs {
+    float* pos;
+    float* vel;
+    void* psi;
+};
+
+template <typename T, int N, int L, bool PV, bool PS>
+__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* __restrict__ in0, const cx<T>* __restrict__ in1, const cx<T>* __restrict__ in2,
+           PlanView<T> pv, ZelArgs za, int ntiles) {
+    constexpr int M = N / 2;
+    constexpr int TPL = PlanInfo<M>::TPL;
+    constexpr int NT = L * TPL;
+    constexpr int V = PlanInfo<M>::V;
+    constexpr int NF = L * M / 2 / NT;  // pairs of complex values per thread and tile
+    static_assert(NF * NT == L * M / 2, "a tile is whole pairs per thread");
+    constexpr int TPC = N * N / L;  // tiles per component
+    __shared__ cx<T> lds[L * M];
+    __shared__ cx<T> twl[N];
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = pv.tw[i];
+    cx<T> r0[NF], r1[NF];
+    auto load = [&](int tile) {
+        const int t = opaque((int)threadIdx.x);
+        const int comp = tile / TPC;
+        const cx<T>* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
+        const cx<T>* src = in + (uint64_t)(tile - comp * TPC) * L * M;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int mm = comp == 0 ? m0 : (comp == 1 ? m1 : 2 * m + e);
-                zel_point<T>(vals[e], mm, pv.origin[comp], pv.cell, pv.offset, pv.wrap, (T)pv.vfac, p[e], u[e]);
+        for (int q = 0; q < NF; ++q) {
+            const int fi = t + q * NT;
+            r0[q] = src[2 * fi];
+            r1[q] = src[2 * fi + 1];
+        }
+    };
+    const uint64_t n3 = (uint64_t)N * N * N;
+    int tile = blockIdx.x;
+    if (tile < ntiles) load(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int comp = tile / TPC;
+        const uint64_t line0 = (uint64_t)(tile - comp * TPC) * L;
+        // recomputed per tile rather than kept live across the loop
+        const int t = opaque((int)threadIdx.x);
+        const int c = t % L, j = t / L;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const int fi = t + q * NT;
+            const int cc = fi / (M / 2), k = 2 * (fi % (M / 2));
+            cx<T> x0 = r0[q], x1 = r1[q];
+            if (comp == 2) {
+                x0 = cscale(x0, (T)k);
+                x1 = cscale(x1, (T)(k + 1));
             }
-            if (za.pos) *reinterpret_cast<float4*>(za.pos + off) = make_float4(p[0], p[1], p[2], p[3]);
-            if (za.vel) *reinterpret_cast<float4*>(za.vel + off) = make_float4(u[0], u[1], u[2], u[3]);
-            if (za.psi) {
-                T* q = static_cast<T*>(za.psi) + off;
-                *reinterpret_cast<cx<T>*>(q) = z0;
-                *reinterpret_cast<cx<T>*>(q + 2) = z1;
+            lds[lidx<L>(k, cc)] = x0;
+            lds[lidx<L>(k + 1, cc)] = x1;
+        }
+        const int next = tile + (int)gridDim.x;
+        load(next < ntiles ? next : tile);
+        __syncthreads();
+        cx<T> v[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = c2r_pack<T, M, L>(lds, twl, (T)0, first_pos<M, 1>(j, i), c);
+        __syncthreads();
+        fft_lines<T, M, L, 1, 2>(v, lds, twl, c, j);
+#pragma unroll
+        for (int i = 0; i < V; ++i) lds[lidx<L>(last_pos<M, 1>(j, i), c)] = v[i];
+        __syncthreads();
+        // float tiles: a rolled loop keeps the kernel within 64 registers (two
+        // work-groups per compute unit); double tiles are bound by LDS anyway
+#pragma unroll(sizeof(T) == 8 ? NF : 1)
+        for (int q = 0; q < NF; ++q) {
+            const int fi = t + q * NT;
+            const int cc = fi / (M / 2), m = 2 * (fi % (M / 2));
+            const cx<T> z0 = lds[lidx<L>(m, cc)], z1 = lds[lidx<L>(m + 1, cc)];
+            int m0, m1;
+            row_coords<true>(line0 + cc, N, m0, m1);
+            const uint64_t off = (uint64_t)comp * n3 + ((uint64_t)m0 * N + m1) * N + 2 * m;
+            if constexpr (PV) {
+                const T vals[4] = {z0.x, z0.y, z1.x, z1.y};
+                float p[4], u[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int mm = comp == 0 ? m0 : (comp == 1 ? m1 : 2 * m + e);
+                    zel_point<T>(vals[e], mm, pv.origin[comp], pv.cell, pv.offset, pv.wrap, (T)pv.vfac, p[e], u[e]);
+                }
+                *reinterpret_cast<float4*>(za.pos + off) = make_float4(p[0], p[1], p[2], p[3]);
+                *reinterpret_cast<float4*>(za.vel + off) = make_float4(u[0], u[1], u[2], u[3]);
+            }
+            if constexpr (PS) {
+                T* o = static_cast<T*>(za.psi) + off;
+                *reinterpret_cast<cx<T>*>(o) = z0;
+                *reinterpret_cast<cx<T>*>(o + 2) = z1;
             }
         }
+        __syncthreads();
     }
 }
 

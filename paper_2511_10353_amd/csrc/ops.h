@@ -36,6 +36,9 @@ struct ExecCtx {
     // (16 float, 8 double) or half of it.
     int p1_lines = 0;
     int z_lines = 0;
+    // work-groups of the last pass, each looping over its share of the tiles
+    // (0 = one per tile)
+    int zel_blocks = 0;
 };
 
 template <typename T>

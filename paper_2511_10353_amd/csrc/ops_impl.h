@@ -142,8 +142,7 @@ hipError_t Ops<T>::fft_inverse(const PlanView<T>& pv, const cx<T>* in, T* out, c
             strided_args<T>(work, nullptr, work, nullptr, nullptr, N * R, 0, 0, R, 0, 0, M + 1), pv, s);
         if (e != hipSuccess) return e;
         const T scale = (T)(1.0 / ((double)N * (double)N * (double)N));
-        k_zinv<T, N, 0, false><<<dim3(N * N / L, 1), L * PlanInfo<M>::TPL, 0, s>>>(
-            work, work, work, M + 1, out, scale, pv, ZelArgs{nullptr, nullptr, nullptr});
+        k_zinv<T, N, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(work, M + 1, out, scale, pv);
         return hipGetLastError();
     });
 }
@@ -290,8 +289,14 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
         GG_TRY(mark(sa, 0))
         GG_TRY((with_lines<T, N>(x.z_lines, LZ, [&](auto lc) -> hipError_t {
             constexpr int L5 = decltype(lc)::value;
-            k_zinv<T, N, 1, true, L5><<<dim3(N * N / L5, 3), L5 * PlanInfo<M>::TPL, 0, sa>>>(
-                b1, b0, b2, M, nullptr, (T)1, pv, ZelArgs{pos, vel, psi});
+            // components 0, 1, 2 are in b1, b0, b2 (P4's outputs)
+            const int ntiles = 3 * (N * N / L5);
+            const int grid = x.zel_blocks > 0 && x.zel_blocks < ntiles ? x.zel_blocks : ntiles;
+            const dim3 gd(grid), bd(L5 * PlanInfo<M>::TPL);
+            const ZelArgs za{pos, vel, psi};
+            if (pos && psi) k_zel<T, N, L5, true, true><<<gd, bd, 0, sa>>>(b1, b0, b2, pv, za, ntiles);
+            else if (pos) k_zel<T, N, L5, true, false><<<gd, bd, 0, sa>>>(b1, b0, b2, pv, za, ntiles);
+            else if (psi) k_zel<T, N, L5, false, true><<<gd, bd, 0, sa>>>(b1, b0, b2, pv, za, ntiles);
             return hipGetLastError();
         })))
         GG_TRY(mark(sa, 1))
@@ -340,8 +345,7 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
         GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
                                                 pv, s)))
         // A5: axis-2 c2r -> d loss / d W (the 1/N^3 is inside tau)
-        k_zinv<T, N, 0, true, LZ><<<dim3(N * N / LZ, 1), LZ * PlanInfo<M>::TPL, 0, s>>>(b0, b0, b0, M, gw, (T)1, pv,
-                                                                                        ZelArgs{nullptr, nullptr, nullptr});
+        k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, gw, (T)1, pv);
         GG_TRY(hipGetLastError())
 #undef GG_TRY
         return hipSuccess;
@@ -373,8 +377,7 @@ hipError_t Ops<T>::density(const PlanView<T>& pv, uint64_t seed, const T* w, T* 
             strided_args<T>(b0, nullptr, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M), pv, s)))
         GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
                                                 pv, s)))
-        k_zinv<T, N, 0, true, LZ><<<dim3(N * N / LZ, 1), LZ * PlanInfo<M>::TPL, 0, s>>>(b0, b0, b0, M, delta, (T)1, pv,
-                                                                                        ZelArgs{nullptr, nullptr, nullptr});
+        k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, delta, (T)1, pv);
         GG_TRY(hipGetLastError())
 #undef GG_TRY
         return hipSuccess;
