@@ -560,7 +560,22 @@ struct StridedArgs {
     int ncb;  // column blocks per outer index in this launch
     int cb0;  // first column block of this launch
     int o0;   // first outer index of this launch
+    int xgroup;  // tile order across XCDs (see xcd_tile)
 };
+
+// Tile of work-group b in a grid of nb work-groups.  The dispatcher hands
+// work-group b to XCD b % 8; with xgroup = g > 0 each XCD takes groups of g
+// consecutive tiles (g = 2: the two column blocks of neighbouring 128-byte
+// chunks of the same rows), with g = 0 one contiguous range of nb / 8 tiles.
+// A bijection on [0, nb): the last nb mod 8g work-groups keep their index.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int xgroup) {
+    const unsigned g = xgroup > 0 ? (unsigned)xgroup : nb / 8u;
+    if (g == 0) return b;
+    const unsigned full = nb / (8u * g) * (8u * g);
+    if (b >= full) return b;
+    const unsigned x = b & 7u, k = b >> 3;
+    return ((k / g) * 8u + x) * g + k % g;
+}
 
 template <typename T, int N, int MODE, int L, bool PBLK>
 __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T> a, PlanView<T> pv) {
@@ -575,8 +590,9 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
     // wave instruction sit in one blocked 8-row group
     constexpr bool RX = RowExchange<T, N, L>::value && !PBLK;
     const int c = t % L, j = line_thread<RX, L>(t);
-    const int o = a.o0 + (int)(blockIdx.x / a.ncb);
-    const int col0 = (a.cb0 + (int)(blockIdx.x % a.ncb)) * L;
+    const unsigned tid = xcd_tile(blockIdx.x, gridDim.x, a.xgroup);
+    const int o = a.o0 + (int)(tid / a.ncb);
+    const int col0 = (a.cb0 + (int)(tid % a.ncb)) * L;
     const int col = col0 + c;
     const bool valid = col < a.ncols;
     // wave-uniform tile base; lanes past the last column of a ragged tile

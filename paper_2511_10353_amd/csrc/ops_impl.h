@@ -77,7 +77,7 @@ template <typename T>
 StridedArgs<T> strided_args(const cx<T>* in0, const cx<T>* in1, cx<T>* out0, cx<T>* out1, cx<T>* out2, int64_t ohi,
                             int64_t olo, int oshift, int64_t pstride, int64_t phi, int64_t plo, int ncols,
                             const cx<T>* in2 = nullptr) {
-    return StridedArgs<T>{in0, in1, in2, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0};
+    return StridedArgs<T>{in0, in1, in2, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0, 2};
 }
 
 // Launches tiles o in [o0, o0 + no) x column blocks [cb0, cb0 + nb) (nb = 0:
@@ -224,9 +224,13 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
     if ((e = (expr)) != hipSuccess) return e;
         // spectra rows are blocked: row ((m0 / 8) N + k1) 8 + m0 % 8 holds k2 in [0, M)
         const int64_t H = (int64_t)8 * N * M;  // one m0 / 8 slab
-        const StridedArgs<T> a2 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
+        StridedArgs<T> a2 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
         const StridedArgs<T> a3 = strided_args<T>(b0, nullptr, b1, b2, nullptr, 8 * M, 0, 0, 0, H, M, M);
-        const StridedArgs<T> a4 = strided_args<T>(b1, b2, b1, b0, b2, H, M, 3, 8 * M, 0, 0, M);
+        StridedArgs<T> a4 = strided_args<T>(b1, b2, b1, b0, b2, H, M, 3, 8 * M, 0, 0, M);
+        // XCD tile orders measured best at 1024^3: P2 one range per XCD, P3 pairs,
+        // P4 pairs (float) or one range per XCD (double)
+        a2.xgroup = 0;
+        a4.xgroup = sizeof(T) == 8 ? 0 : 2;
         const int xh = (N / 8) / NC;                           // m0 / 8 values per slab
         const int nb = ((M + Tile<T>::L - 1) / Tile<T>::L) / NC;  // column blocks per chunk
         if (NC > 1) {
