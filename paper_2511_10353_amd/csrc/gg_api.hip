@@ -57,8 +57,8 @@ struct gg_plan {
     // tile choices of the fused path (0 = built-in; set by gg_plan_set_tuning
     // or gg_plan_autotune)
     int p1_lines = 0, z_lines = 0;
-    // work-groups of the last pass (16 per compute unit of the plan's device)
-    int zel_blocks = 0;
+    // compute units of the plan's device (grids of the persistent passes)
+    int cus = 0;
     // pipelined launch of the fused path: auxiliary stream, dependency events
     int nchunk = 1;
     hipStream_t aux = nullptr;
@@ -82,7 +82,7 @@ gg::ExecCtx fused_ctx(gg_plan* p, void* stream) {
     x.nchunk = p->nchunk;
     x.p1_lines = p->p1_lines;
     x.z_lines = p->z_lines;
-    x.zel_blocks = p->zel_blocks;
+    x.cus = p->cus;
     return x;
 }
 
@@ -216,7 +216,7 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
         delete p;
         return fail_hip(e, "hipGetDevice / compute unit count");
     }
-    p->zel_blocks = 16 * (cus > 0 ? cus : 256);
+    p->cus = cus > 0 ? cus : 256;
     const size_t es = elem_size(dtype);
     const int half = p->n / 2;
     p->ntau = 3LL * half * half + 1;

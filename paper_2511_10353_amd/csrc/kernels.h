@@ -793,6 +793,117 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 }
 
 // ---------------------------------------------------------------------------
+// P3 for float plans as a persistent kernel (same arithmetic as SMODE_XFILT
+// above).  Work-group b takes tiles b, b + G, ... (G = gridDim.x, tile order
+// across XCDs by xcd_tile over the launch's ntiles tiles).  Once F is
+// stored, the registers of its line are free: the next tile's input is
+// loaded into them and is in flight while G is transformed and stored.  The
+// twiddles are copied into LDS once, so that no global load follows the
+// prefetch (loads complete in order).  LDS: tile 128 KB + twiddles 8 KB +
+// tau segments 15 KB at N = 1024, one work-group per compute unit.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int L>
+__global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_xfilt(StridedArgs<T> a, PlanView<T> pv, int ntiles) {
+    static_assert(std::is_same_v<T, float>, "double tiles leave no LDS for the twiddle table");
+    constexpr int V = PlanInfo<N>::V;
+    constexpr int TPL = PlanInfo<N>::TPL;
+    constexpr int RF = PlanInfo<N>::template first_radix<-1>();
+    constexpr int RL = PlanInfo<N>::template last_radix<1>();
+    constexpr bool SPLIT = (TPL % 8 == 0) && (N % 128 == 0);
+    __shared__ cx<T> lds[L * N];
+    __shared__ cx<T> twl[N];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = pv.tw[i];
+    const TauLookup<T> taul = tau_lookup(pv);
+    auto poff = [&](int p) -> int64_t { return (int64_t)(p >> 3) * a.phi + (int64_t)(p & 7) * a.plo; };
+    struct TileAt {
+        int o, col, cl;
+        bool valid;
+        int64_t base;  // wave-uniform
+    };
+    auto tile_at = [&](int u, int c) -> TileAt {
+        const unsigned tid = xcd_tile((unsigned)u, (unsigned)ntiles, a.xgroup);
+        TileAt r;
+        r.o = a.o0 + (int)(tid / a.ncb);
+        const int col0 = (a.cb0 + (int)(tid % a.ncb)) * L;
+        r.col = col0 + c;
+        r.valid = r.col < a.ncols;
+        r.cl = r.valid ? c : a.ncols - 1 - col0;
+        r.base = (int64_t)(r.o >> a.oshift) * a.ohi + (int64_t)(r.o & ((1 << a.oshift) - 1)) * a.olo + col0;
+        return r;
+    };
+    // slot i of line thread jj (layout radix R), as in k_strided
+    auto at = [&](auto* base, const TileAt& tl, int i, int R, int jj) {
+        const int rowc = TPL * (i / R) + (i % R) * (N / R);
+        using P = decltype(base);
+        if constexpr (SPLIT) {
+            auto* slot = base + (tl.base + poff(rowc));
+            using B = std::conditional_t<std::is_const_v<std::remove_pointer_t<P>>, const char*, char*>;
+            const uint32_t laneb = (uint32_t)((poff(jj) + tl.cl) * (int64_t)sizeof(cx<T>));
+            return reinterpret_cast<P>(reinterpret_cast<B>(slot) + laneb);
+        } else {
+            return base + (tl.base + tl.cl + poff(jj + rowc));
+        }
+    };
+    cx<T> v[V];
+    int u = blockIdx.x;
+    {
+        const int t = opaque((int)threadIdx.x);
+        const TileAt tl = tile_at(u < ntiles ? u : 0, t % L);
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = *at(a.in0, tl, i, RF, t / L);
+    }
+    __syncthreads();
+    for (; u < ntiles; u += gridDim.x) {
+        const int t = opaque((int)threadIdx.x);
+        const int c = t % L, j = t / L;
+        const TileAt tl = tile_at(u, c);
+        fft_lines<T, N, L, -1, 1>(v, lds, twl, c, j);
+        const int s1 = signed_mode(tl.o, N);
+        const int s2 = tl.col;
+        const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
+        const T dline = pv.deconv ? cic_deconv<T>(s1, N) * cic_deconv<T>(s2, N) : (T)1;
+        cx<T> g[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const int k0 = last_pos<N, -1>(j, i);
+            const int s0 = signed_mode(k0, N);
+            const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
+            const bool zero = line_zero || (k0 == N / 2) || n2 < pv.n2_lo || n2 >= pv.n2_hi;
+            T tau = taul(zero ? 0 : n2) * (T)pv.amp_scale;  // tau(0) = 0: mean and Nyquist vanish
+            if (pv.deconv) tau *= cic_deconv<T>(s0, N) * dline;
+            g[i] = mul_i(cscale(v[i], tau));
+            v[i] = cscale(g[i], (T)s0);
+        }
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            fft_lines<T, N, L, 1, 1>(v, lds, twl, cc, jj);
+            const TileAt to = tile_at(opaque(u), cc);
+            if (to.valid) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) *at(a.out0, to, i, RL, jj) = v[i];
+            }
+        }
+        {
+            // the next tile (this one again after the last) into v
+            const int jj = opaque(j), cc = opaque(c);
+            const int un = u + (int)gridDim.x;
+            const TileAt tn = tile_at(un < ntiles ? un : u, cc);
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = *at(a.in0, tn, i, RF, jj);
+        }
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            fft_lines<T, N, L, 1, 1>(g, lds, twl, cc, jj);
+            const TileAt to = tile_at(opaque(u), cc);
+            if (to.valid) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) *at(a.out1, to, i, RL, jj) = g[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Eq. 5 window on a plain half spectrum (rows (k0, k1), k2 in [0, N/2]):
 // modes with n^2 >= n2_max are zeroed, the others divided by the CiC window
 // prod_j sinc^2(pi s_j / N) if deconv is set.

@@ -36,9 +36,9 @@ struct ExecCtx {
     // (16 float, 8 double) or half of it.
     int p1_lines = 0;
     int z_lines = 0;
-    // work-groups of the last pass, each looping over its share of the tiles
-    // (0 = one per tile)
-    int zel_blocks = 0;
+    // compute units of the device: the persistent passes (P3 for float
+    // plans, P5) size their grids by it (0 = one work-group per tile)
+    int cus = 0;
 };
 
 template <typename T>

@@ -103,6 +103,27 @@ hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipSt
     return hipGetLastError();
 }
 
+// P3 of float plans: the persistent k_xfilt over column blocks [cb0, cb0 + nb)
+// of every outer index (blocked rows), with launch_strided's checks; one
+// work-group per compute unit (cus = 0: one per tile).
+template <typename T, int N>
+hipError_t launch_xfilt(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStream_t s, int cb0, int nb, int cus) {
+    constexpr int L = Tile<T>::L;
+    StridedArgs<T> a = a0;
+    const int ncb_all = (a.ncols + L - 1) / L;
+    if (cb0 < 0 || nb < 1 || cb0 + nb > ncb_all) return hipErrorInvalidValue;
+    a.ncb = nb;
+    a.cb0 = cb0;
+    a.o0 = 0;
+    const int jmax = PlanInfo<N>::TPL - 1;
+    const int64_t prow = (int64_t)(jmax >> 3) * a.phi + (int64_t)(jmax & 7) * a.plo;
+    if (a.ncols < 1 || (prow + L) * (int64_t)sizeof(cx<T>) >= (int64_t)1 << 32) return hipErrorInvalidValue;
+    const int ntiles = N * nb;
+    const int grid = cus > 0 && cus < ntiles ? cus : ntiles;
+    k_xfilt<T, N, L><<<grid, L * PlanInfo<N>::TPL, 0, s>>>(a, pv, ntiles);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t Ops<T>::noise(const PlanView<T>& pv, uint64_t seed, uint32_t stream_id, T* w, hipStream_t s) {
     const uint64_t n3 = (uint64_t)pv.n * pv.n * pv.n;
@@ -274,7 +295,11 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
         for (int q = 0; q < NC; ++q) {
             launch = 2 * NC + q;
             GG_TRY(mark(sa, 0))
-            GG_TRY((launch_strided<T, N, SMODE_XFILT, true>(a3, pv, sa, 0, 0, nb * q, nb)))
+            if constexpr (std::is_same_v<T, float>) {
+                GG_TRY((launch_xfilt<T, N>(a3, pv, sa, nb * q, nb, x.cus)))
+            } else {
+                GG_TRY((launch_strided<T, N, SMODE_XFILT, true>(a3, pv, sa, 0, 0, nb * q, nb)))
+            }
             GG_TRY(mark(sa, 1))
             if (NC > 1) {
                 GG_TRY(hipEventRecord(x.sync[NC + 2 + q], sa))
@@ -295,7 +320,7 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
             constexpr int L5 = decltype(lc)::value;
             // components 0, 1, 2 are in b1, b0, b2 (P4's outputs)
             const int ntiles = 3 * (N * N / L5);
-            const int grid = x.zel_blocks > 0 && x.zel_blocks < ntiles ? x.zel_blocks : ntiles;
+            const int grid = x.cus > 0 && 16 * x.cus < ntiles ? 16 * x.cus : ntiles;
             const dim3 gd(grid), bd(L5 * PlanInfo<M>::TPL);
             const ZelArgs za{pos, vel, psi};
             if (pos && psi) k_zel<T, N, L5, true, true><<<gd, bd, 0, sa>>>(b1, b0, b2, pv, za, ntiles);
