@@ -50,6 +50,11 @@
  *   allocation (GG_ERR_OUT_OF_MEMORY, the earlier ones freed); with
  *   GG_FAULT_INJECT=launch, gg_make_ic returns GG_ERR_HIP without launching.
  *   The variable is read on each call; unset, it changes nothing.
+ * - GG_CUS=k (1 <= k < the device's compute units), read by gg_plan_create:
+ *   the plan sizes the grids of its persistent passes (P3 of float plans,
+ *   P5) as if the device had k compute units, so that each work-group loops
+ *   over more tiles.  Results do not depend on it; tests use it to exercise
+ *   those loops at small lattices.
  * - A plan is read-only after gg_plan_create, except for the timing records
  *   of gg_timing_enable.  gg_noise, gg_fft3d, gg_filter and gg_zeldovich on one
  *   plan may run from several streams (each with its own buffers);

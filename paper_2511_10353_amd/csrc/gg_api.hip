@@ -217,6 +217,11 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
         return fail_hip(e, "hipGetDevice / compute unit count");
     }
     p->cus = cus > 0 ? cus : 256;
+    // GG_CUS (tests): size the persistent passes' grids for fewer compute units
+    if (const char* env = std::getenv("GG_CUS")) {
+        const int want = std::atoi(env);
+        if (want >= 1 && want < p->cus) p->cus = want;
+    }
     const size_t es = elem_size(dtype);
     const int half = p->n / 2;
     p->ntau = 3LL * half * half + 1;
