@@ -432,8 +432,10 @@ struct ZelArgs {
 };
 
 template <typename T, int N, int L, bool PV, bool PS>
-__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* __restrict__ in0, const cx<T>* __restrict__ in1, const cx<T>* __restrict__ in2,
-           PlanView<T> pv, ZelArgs za, int ntiles) {
+__global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* __restrict__ in0,
+                                                                  const cx<T>* __restrict__ in1,
+                                                                  const cx<T>* __restrict__ in2, PlanView<T> pv,
+                                                                  ZelArgs za, int ntiles) {
     constexpr int M = N / 2;
     constexpr int TPL = PlanInfo<M>::TPL;
     constexpr int NT = L * TPL;
