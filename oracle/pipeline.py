@@ -14,8 +14,9 @@ mode with |s_j| = N/2 on any axis (keeps the field exactly real, and
 div psi = -delta, curl psi = 0 mode by mode).
 
 Sec. 2.2, Eq. (3): particle at lattice point q_j = (m_j + offset) Delta with
-Delta = L/N moves to x_j = q_j + psi_j (sum in float64, wrapped once into
-[0, L), rounded to float32, a rounded value equal to L mapped to 0), with
+Delta = L/N moves to x_j = q_j + psi_j (sum in float64, wrapped periodically
+into [0, L) as x - L floor(x/L), rounded to float32, a rounded value equal to L
+mapped to 0), with
 velocity v_j = a H f psi_j.  The paper's minus sign in Eq. (3) belongs to its
 opposite Fourier sign convention; with the convention above the growing mode
 moves particles along +psi.
@@ -89,10 +90,18 @@ def lattice(n, box, offset, axis):
     return (m + offset) * delta
 
 
+def periodic_wrap(x, box):
+    """x - L floor(x/L) in float64: the periodic image of x in [0, L).  The
+    quotient is rounded, so a result that lands on L or just below 0 is moved
+    by one more period."""
+    x = np.asarray(x, dtype=np.float64)
+    x = x - box * np.floor(x / box)
+    return np.where(x < 0.0, x + box, np.where(x >= box, x - box, x))
+
+
 def positions(psi_j, n, box, offset, axis):
     """Eq. (3) for one component: float32 positions in [0, L)."""
-    x = lattice(n, box, offset, axis) + np.asarray(psi_j, dtype=np.float64)
-    x = np.where(x < 0.0, x + box, np.where(x >= box, x - box, x))
+    x = periodic_wrap(lattice(n, box, offset, axis) + np.asarray(psi_j, dtype=np.float64), box)
     out = x.astype(np.float32)
     return np.where(out >= np.float32(box), np.float32(0.0), out)
 

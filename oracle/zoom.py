@@ -95,7 +95,7 @@ def particles(psi, n, cell, origin_box, box0, cosmo, offset=0.5):
         shape[j] = n
         q = origin_box[j] + (np.arange(n, dtype=np.float64).reshape(shape) + offset) * cell
         x = q + np.asarray(psi[j], dtype=np.float64)
-        x = np.where(x < 0.0, x + box0, np.where(x >= box0, x - box0, x))
+        x = pipeline.periodic_wrap(x, box0)
         xf = x.astype(np.float32)
         pos.append(np.where(xf >= np.float32(box0), np.float32(0.0), xf))
     vel = (cosmology.velocity_factor(cosmo) * np.asarray(psi, dtype=np.float64)).astype(np.float32)

@@ -108,3 +108,33 @@ def test_velocity_factor():
     lcdm = cosmology.Cosmology()
     assert abs(cosmology.velocity_factor(lcdm) - 550.4550) < 5e-4
     assert cosmology.growth(0.0) == 1.0
+
+
+def _growth_integral(a, omega_m=1.0):
+    # Linear growing mode of a matter + Lambda universe (Heath 1977):
+    # D(a) proportional to E(a) int_0^a da' / (a' E(a'))^3, E = H/H0.  It is
+    # the growing solution of the linear growth equation, computed here by
+    # quadrature, independently of the closed form used by the oracle.
+    def e_of(x):
+        return math.sqrt(omega_m / x ** 3 + 1.0 - omega_m)
+
+    val = integrate.quad(lambda x: 1.0 / (x * e_of(x)) ** 3, 0.0, a, epsabs=0, epsrel=1e-13, limit=200)[0]
+    return e_of(a) * val
+
+
+@pytest.mark.parametrize("z", [0.0, 1.0, 9.0, 100.0])
+def test_growth_is_the_matter_dominated_growing_mode(z):
+    # Einstein-de Sitter (Omega_m = 1): the growing mode normalised to D(0) = 1
+    # is the scale factor; a wrong power of (1 + z) fails at z = 1 already
+    want = _growth_integral(1.0 / (1.0 + z)) / _growth_integral(1.0)
+    assert abs(cosmology.growth(z) / want - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("z", [0.0, 1.0, 100.0])
+def test_sigma8_of_the_spectrum_at_z_init(z):
+    # sigma_8 of P(k, z) itself: the z = 0 value 0.8 scaled by the growing
+    # mode (a, from the quadrature above), so P carries D^2 and not D
+    c = cosmology.Cosmology(z_init=z)
+    s = math.sqrt(cosmology.sigma_r_squared(lambda k: cosmology.power(k, c)))
+    d = _growth_integral(1.0 / (1.0 + z)) / _growth_integral(1.0)
+    assert abs(s / (0.8 * d) - 1.0) < 1e-10

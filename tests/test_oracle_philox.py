@@ -124,3 +124,24 @@ def test_avalanche_on_counter_bit():
     # 128 output bits: about half flip on average
     for f in flips:
         assert abs(f - 64.0) < 1.0
+
+
+def test_weyl_increments_from_their_irrationals():
+    # The key schedule adds floor(2^32 (sqrt(5) - 1)/2) (the golden ratio's
+    # fractional part) and floor(2^32 (sqrt(3) - 1)) each round (Salmon et
+    # al., SC'11, on Philox).  Exact integer square roots: isqrt(5 * 2^64) is
+    # floor(2^32 sqrt 5), and floor(floor(y)/2) = floor(y/2) for any y >= 0.
+    import math
+    w0 = (math.isqrt(5 << 64) - (1 << 32)) >> 1
+    w1 = math.isqrt(3 << 64) - (1 << 32)
+    assert philox.W0 == w0
+    assert philox.W1 == w1
+
+
+def test_round_multipliers():
+    # The two multipliers are the published search results (Salmon et al.,
+    # SC'11, for Philox-4x32); they have no closed form, so they are pinned by a
+    # second transcription here and by being odd (a round is a bijection only
+    # then: the inversion test above needs their inverses mod 2^32).
+    assert (philox.M0, philox.M1) == (0xD2511F53, 0xCD9E8D57)
+    assert philox.M0 & 1 and philox.M1 & 1

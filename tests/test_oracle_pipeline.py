@@ -154,6 +154,26 @@ def test_positions_wrap_into_box():
     assert pipeline.positions(psi, n, box, 0.5, 0)[-1, 0, 0] == 0.0
 
 
+@pytest.mark.parametrize("periods", [-3, -2, 2, 5])
+def test_positions_wrap_several_periods(periods):
+    # displacements of several box lengths land on the same periodic image:
+    # exact multiples of L (L a power of two and psi of 26 bits, so every sum is exact) move
+    # nothing, and the image lies in [0, L)
+    n, box = 8, 64.0
+    rng = np.random.default_rng(periods + 10)
+    psi = np.round(rng.uniform(-0.9, 0.9, (n, n, n)) * 2.0 ** 20) * 2.0 ** -20 * box  # 26-bit values
+    base = pipeline.positions(psi, n, box, 0.5, 1)
+    moved = pipeline.positions(psi + periods * box, n, box, 0.5, 1)
+    assert np.array_equal(base, moved)
+    assert moved.min() >= 0 and moved.max() < box
+    # the image is q + psi - L floor((q + psi)/L) evaluated exactly
+    q = (np.arange(n).reshape(1, n, 1) + 0.5) * (box / n)
+    x = q + psi + periods * box
+    want = np.array([float(v) % box for v in x.ravel()]).reshape(x.shape).astype(np.float32)
+    want = np.where(want >= np.float32(box), np.float32(0.0), want)
+    assert np.array_equal(moved, want)
+
+
 def test_linearity_translation_reflection():
     n, box = 16, 100.0
     w = noise.noise_grid(n, 21)

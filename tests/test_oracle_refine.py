@@ -216,3 +216,96 @@ def test_three_halves_combine_whole_box_limit():
     psi = refine.combine(wp, wc, box, COSMO, r_s)
     full = np.stack(pipeline.displacement_fields(wc, 24, box, COSMO))
     assert np.abs(psi - full).max() < 1e-13 * np.abs(full).max()
+
+
+def _shape_basis(e1_shape):
+    # four-cell basis from its defining shapes (App. A): E_0 constant; E_1 the
+    # given shape, odd about the patch centre and increasing like F_1; E_2 the
+    # even function orthogonal to E_0; E_3 the odd function orthogonal to E_1
+    # (E_2 and E_3 follow from Eq. A.1), signs as printed (E_2(0) < 0 < E_3(0))
+    k = np.arange(4) - 1.5
+    e0 = np.full(4, 0.5)
+    e1 = np.asarray(e1_shape, dtype=np.float64)
+    e1 = e1 / np.linalg.norm(e1) * np.sign(e1 @ k)
+    e2 = np.array([-1.0, 1.0, 1.0, -1.0]) / 2.0  # even: [a, b, b, a], 2a + 2b = 0
+    c, d = e1[0], e1[1]  # odd [c', d', -d', -c'] orthogonal to [c, d, -d, -c]
+    e3 = np.array([d, -c, c, -d])
+    e3 = e3 / np.linalg.norm(e3) * np.sign(d)
+    return np.stack([e0, e1, e2, e3])
+
+
+def test_linear_basis_from_its_shape():
+    # Eq. A.20-A.23: E'_1 varies linearly with the child cell index
+    want = _shape_basis(np.arange(4) - 1.5)
+    assert np.abs(refine.E_BASIS["linear"] - want).max() < 1e-15
+
+
+def test_sine_basis_from_its_shape():
+    # Eq. A.24-A.27: E''_1 is a sine of period one patch sampled at the four
+    # cell centres (k + 1/2)/4 of the patch, with the sign that makes it rise
+    x = (np.arange(4) + 0.5) / 4.0
+    want = _shape_basis(-np.sin(2.0 * math.pi * x))
+    assert np.abs(refine.E_BASIS["sine"] - want).max() < 1e-15
+
+
+def _fig_a6_curve(variant, n_low):
+    # Expected |D(n)|^2 of the difference D = DFT_H(n) / sqrt(r) - DFT_L(n)
+    # between a 1D white noise of n_low cells and its refinement (r = N_H/N_L
+    # times more cells), for the low-resolution modes 0 < n < n_low/2.  Both
+    # DFTs are plain (unnormalised, each lattice indexed from its cell 0).  D
+    # is linear in the parent values and the new coefficients, all i.i.d.
+    # unit Gaussians, and patches are independent, so E|D|^2 is the patch
+    # count times the sum of |coefficient|^2 of one patch's sources.
+    nl, nh = refine.patch_sizes(variant)
+    e, f = refine.E_BASIS[variant], refine.F_BASIS[nl]
+    n = np.arange(1, n_low // 2)
+    ph_l = np.exp(-2j * math.pi * np.outer(n, np.arange(nl)) / n_low)
+    ph_h = np.exp(-2j * math.pi * np.outer(n, np.arange(nh)) / (n_low * nh // nl)) / math.sqrt(nh / nl)
+    total = np.zeros(n.size)
+    for m in range(nl):  # parent value V_m enters the child through a_i = sum_m V_m F_i(m)
+        total += np.abs(ph_h @ (f[:, m] @ e[:nl]) - ph_l[:, m]) ** 2
+    for j in range(nl, nh):  # new coefficient j
+        total += np.abs(ph_h @ e[j]) ** 2
+    return n, total * (n_low // nl)
+
+
+def test_fig_a6_relations():
+    # App. A, Fig. A.6 (1D noise of 1024 cells refined by a factor 2; the paper
+    # averages 10^6 realisations, the expectation is taken exactly here).  The
+    # mean amplitude of a circular complex Gaussian is sqrt(pi)/2 times its
+    # r.m.s., so ratios of the curves are ratios of sqrt(E|D|^2).  Printed
+    # relations: HR and the sine variant identical; A.10-A.13 0.3 % below the
+    # linear variant on average and 0.7 % below at k/k_Ny > 0.5; HR and sine
+    # 16 % above the other two on average.
+    n_low = 1024
+    n, lin = _fig_a6_curve("linear", n_low)
+    amp = {v: np.sqrt(_fig_a6_curve(v, n_low)[1]) for v in ("hr", "4", "linear", "sine")}
+    assert np.abs(amp["hr"] / amp["sine"] - 1.0).max() < 1e-12
+    r = amp["4"] / amp["linear"]
+    assert 0.0025 < 1.0 - r.mean() < 0.0035
+    assert 0.0065 < 1.0 - r[n / (n_low // 2) > 0.5].mean() < 0.0075
+    for other in ("4", "linear"):
+        assert 0.15 < (amp["hr"] / amp[other]).mean() - 1.0 < 0.17
+
+
+@pytest.mark.parametrize("variant", ["hr", "4", "sine"])
+def test_fig_a6_expectation_matches_realisations(variant):
+    # the exact expectation above against realisations refined by the
+    # oracle's patch code (1D patches embedded as F_0 F_0 along axes 1, 2)
+    n_low, reps = 256, 256
+    nl, nh = refine.patch_sizes(variant)
+    rng = np.random.default_rng(61)
+    lowres = rng.standard_normal((reps, n_low))
+    p = n_low // nl
+    f0 = refine.F_BASIS[nl][0]
+    v = np.einsum("pm,n,l->pmnl", lowres.reshape(reps * p, nl), f0, f0)
+    new = np.zeros((reps * p, nh, nh, nh))
+    new[:, nl:, 0, 0] = rng.standard_normal((reps * p, nh - nl))
+    e0 = refine.E_BASIS[variant][0]
+    child = (refine.expand_patches(v, new, variant)[:, :, 0, 0] / (e0[0] * e0[0])).reshape(reps, p * nh)
+    d = np.fft.fft(child, axis=1)[:, 1:n_low // 2] / math.sqrt(nh / nl) - np.fft.fft(lowres, axis=1)[:, 1:n_low // 2]
+    got = (np.abs(d) ** 2).mean(axis=0)
+    _, want = _fig_a6_curve(variant, n_low)
+    # bands of 16 modes (n = 1 .. 112): relative standard error 1/sqrt(reps * 16)
+    gb, wb = got[:112].reshape(-1, 16).mean(axis=1), want[:112].reshape(-1, 16).mean(axis=1)
+    assert np.abs(gb / wb - 1.0).max() < 5.0 / math.sqrt(reps * 16)
