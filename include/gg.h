@@ -93,8 +93,8 @@ typedef struct {
  * (BBKS fit, Gamma = omega_m h), sigma_8 at z = 0, Einstein-de Sitter growth
  * D = 1/(1+z), flat-LCDM H(a), f = 1 (Sec. 2.1 footnote; Sec. 2.2).
  * amp > 0 uses A = amp instead of the sigma_8 normalisation.
- * lattice_offset is the Lagrangian point inside a cell, in cells (0.5 puts
- * particles at cell centres as Sec. 2.2 describes). */
+ * lattice_offset is the Lagrangian point inside a cell, in cells, in [0, 1)
+ * (0.5 puts particles at cell centres as Sec. 2.2 describes). */
 typedef struct {
     double omega_m;
     double h;
@@ -158,9 +158,9 @@ gg_status gg_fft3d(const gg_plan* plan, int dir, const void* in, void* out, void
 gg_status gg_filter(const gg_plan* plan, const void* spec_in, void* psi_spec, void* delta_spec, void* stream);
 
 /* Eq. (3): from three displacement fields psi (3 consecutive R arrays),
- * writes float32 positions x_j = wrap_L(q_j + psi_j) (sum in FP64, wrapped
- * once into [0, L), a value rounding to L stored as 0) and velocities
- * v_j = a H f psi_j, q_j = (m_j + lattice_offset) L/N.  Requires |psi| < L. */
+ * writes float32 positions x_j = wrap_L(q_j + psi_j) (sum in FP64, the
+ * periodic image x - L floor(x/L) in [0, L), a value rounding to L stored as
+ * 0) and velocities v_j = a H f psi_j, q_j = (m_j + lattice_offset) L/N. */
 gg_status gg_zeldovich(const gg_plan* plan, const void* psi, float* pos, float* vel, void* stream);
 
 /* The whole path from a seed (stream_id 0): noise, forward transform, filter,

@@ -200,7 +200,8 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     if (!(c.z_init > -1) || !std::isfinite(c.z_init)) return fail(GG_ERR_INVALID_ARG, "z_init must be > -1");
     if (!(c.amp >= 0) || !std::isfinite(c.amp)) return fail(GG_ERR_INVALID_ARG, "amp must be >= 0");
     if (c.amp == 0 && !(c.sigma8 > 0)) return fail(GG_ERR_INVALID_ARG, "sigma8 must be > 0 when amp = 0");
-    if (!std::isfinite(c.lattice_offset)) return fail(GG_ERR_INVALID_ARG, "lattice_offset must be finite");
+    if (!(c.lattice_offset >= 0 && c.lattice_offset < 1))
+        return fail(GG_ERR_INVALID_ARG, "lattice_offset must be in [0, 1) cells");
 
     gg_plan* p = new (std::nothrow) gg_plan();
     if (!p) return fail(GG_ERR_OUT_OF_MEMORY, "host allocation failed");

@@ -321,7 +321,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
 }
 
 // ---------------------------------------------------------------------------
-// Eq. (3) for one value: position (sum in binary64, one wrap into [0, L),
+// Eq. (3) for one value: position (sum in binary64, periodic image in [0, L),
 // float rounding, L -> 0) and velocity a H f psi in the path's type.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -330,8 +330,13 @@ __device__ __forceinline__ void zel_point(T psi, int m, double origin, double ce
 #pragma clang fp contract(off)
     const double q = origin + ((double)m + offset) * cell;
     double x = q + (double)psi;
-    if (x < 0.0) x = x + box;
-    else if (x >= box) x = x - box;
+    if (x < 0.0 || x >= box) {
+        // periodic image x - L floor(x/L); the rounded quotient can leave the
+        // result on L or just below 0, which one more period corrects
+        x = x - box * floor(x / box);
+        if (x < 0.0) x = x + box;
+        else if (x >= box) x = x - box;
+    }
     float xf = (float)x;
     if (xf >= (float)box) xf = 0.0f;
     pos = xf;

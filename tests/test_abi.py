@@ -94,7 +94,9 @@ def test_unsupported_sizes_rejected(lib, n):
 @pytest.mark.parametrize("kw,box,dtype", [({}, 0.0, 0), ({}, -1.0, 0), ({}, float("inf"), 0), ({}, 100.0, 2),
                                           ({"omega_m": 0.0}, 100.0, 0), ({"h": -0.7}, 100.0, 0),
                                           ({"z_init": -1.0}, 100.0, 0), ({"sigma8": 0.0}, 100.0, 0),
-                                          ({"amp": -1.0}, 100.0, 0), ({"lattice_offset": float("nan")}, 100.0, 0)])
+                                          ({"amp": -1.0}, 100.0, 0), ({"lattice_offset": float("nan")}, 100.0, 0),
+                                          ({"lattice_offset": 1.0}, 100.0, 0), ({"lattice_offset": -0.25}, 100.0, 0),
+                                          ({"lattice_offset": 1024.5}, 100.0, 1)])
 def test_bad_arguments_rejected(lib, kw, box, dtype):
     st, msg = _create(lib, box=box, dtype=dtype, **kw)
     assert st == 1 and msg

@@ -134,6 +134,22 @@ def test_zeldovich(dtype):
     assert pos.min() >= 0 and pos.max() < box
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_zeldovich_wraps_several_periods(dtype):
+    # displacements of up to three box lengths: positions are the periodic
+    # image x - L floor(x/L) of the oracle, bit for bit
+    n, box = 32, 64.0
+    p = _plan(n, box, dtype)
+    rng = np.random.default_rng(17)
+    psi = (np.round(rng.uniform(-3.0, 3.0, (3, n, n, n)) * 2.0 ** 16) * 2.0 ** -16 * box).astype(NPDT[dtype])
+    say(f"zeldovich wrap {dtype}: |psi|/L up to {np.abs(psi).max() / box:.2f}")
+    pos, _ = p.zeldovich(torch.from_numpy(psi).cuda())
+    pos = pos.cpu().numpy()
+    for j in range(3):
+        assert pos[j].tobytes() == opipe.positions(psi[j], n, box, 0.5, j).tobytes()
+    assert pos.min() >= 0 and pos.max() < box
+
+
 def _check_ic(n, box, seed, dtype, pos, vel, psi):
     o_pos, o_vel, o_psi = oracle_ic(n, box, seed, dtype)
     for j in range(3):
