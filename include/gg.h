@@ -275,6 +275,31 @@ gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const
 gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t origin[3], int32_t n_dst, gg_dtype dtype,
                                 const void* src, void* dst, void* stream);
 
+/* The integer mode bound of the top hat f(k r_s) = [k r_s < 1] of Eq. 4-5 on
+ * a periodic box of side `box`: with k = (2 pi / box) |n|, k r_s < 1 holds
+ * exactly for the lattice modes with n^2 < ceil((box / (2 pi r_s))^2), the
+ * value returned.  -1 for a box or r_s that is not positive and finite.
+ * Host-only arithmetic, no device work. */
+int64_t gg_cutoff_n2(double box, double r_s);
+
+/* Full-box resolution increase (Sec. 2.3, Eq. 4-5, with App. A):
+ *   1. w_child = App. A refinement of w_parent (basis `variant`, new
+ *      coefficients from (seed, stream_id), as gg_refine_noise);
+ *   2. psi = the child's displacements with the filter kept to the small
+ *      scales k r_s >= 1 (Eq. 4);
+ *   3. the parent's displacements of w_parent kept to k r_s < 1 (Eq. 5) and
+ *      divided by the cloud-in-cell window, then added to psi by CiC
+ *      interpolation onto the child's lattice points (as gg_interpolate_add).
+ * parent, child: plans over the same box and dtype with child n = parent n
+ * N_H / N_L.  r_s: cutoff scale in Mpc/h; 0 selects two parent cells (the
+ * paper's choice).  w_parent: R of the parent (read); w_child: R of the child
+ * and psi: 3 R of the child (written); work: gg_workspace_bytes(child) (it
+ * also holds the parent's large-scale fields and transforms).  Buffers
+ * 256-byte aligned, not overlapping.  Launches on `stream` only. */
+gg_status gg_increase_resolution(const gg_plan* parent, const gg_plan* child, const void* w_parent, gg_refine variant,
+                                 uint64_t seed, uint32_t stream_id, double r_s, void* w_child, void* psi, void* work,
+                                 void* stream);
+
 /* Eq. 5 on a real periodic field (R, plan dtype): its transform restricted to
  * n^2 < n2_max (n2_max <= 0: no bound), divided by the cloud-in-cell window
  * if cic_deconvolve is set, transformed back into out (R; may equal field).

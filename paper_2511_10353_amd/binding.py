@@ -94,6 +94,9 @@ _SIGS = {
     "gg_interpolate_add_at": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int, _VP, _VP,
                                               _VP]),
     "gg_lowpass": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP]),
+    "gg_cutoff_n2": (ctypes.c_int64, [ctypes.c_double, ctypes.c_double]),
+    "gg_increase_resolution": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                               ctypes.c_double, _VP, _VP, _VP, _VP]),
     "gg_zeldovich_at": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP]),
     "gg_degrade": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     "gg_zoom_create": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int]),
@@ -507,24 +510,28 @@ def interpolate_add(src, dst):
 
 
 def cutoff_n2(box, r_s):
-    """The integer mode bound of the top hat f(k r_s) = [k r_s < 1]: n^2 < cutoff."""
-    import math
-    return int(math.ceil((box / (2.0 * math.pi * r_s)) ** 2))
+    """gg_cutoff_n2: the mode bound of the top hat [k r_s < 1] (n^2 < cutoff)."""
+    cut = lib().gg_cutoff_n2(float(box), float(r_s))
+    if cut < 0:
+        raise ValueError("box and r_s must be positive and finite")
+    return int(cut)
 
 
-def increase_resolution(parent, child, w_parent, variant="4", seed=0, stream_id=1, r_s=None):
-    """Full-box resolution increase (Sec. 2.3): refine the parent noise, take
-    the child's small scales (Eq. 4) and the parent's large scales (Eq. 5,
-    CiC-interpolated with deconvolution).  Returns (w_child, psi_child)."""
-    if r_s is None:
-        r_s = 2.0 * parent.box / parent.n  # two parent cells
-    cut = cutoff_n2(parent.box, r_s)
-    w_child = refine_noise(w_parent, variant, seed, stream_id)
-    if tuple(w_child.shape) != (child.n,) * 3:
-        raise ValueError("child plan size does not match the refined noise")
-    psi = child.make_displacements(w_child, n2_min=cut)
-    large = parent.make_displacements(w_parent, n2_max=cut, deconvolve=True)
-    interpolate_add(large, psi)
+def increase_resolution(parent, child, w_parent, variant="4", seed=0, stream_id=1, r_s=None, w_child=None, psi=None,
+                        work=None):
+    """gg_increase_resolution (Sec. 2.3, Eq. 4-5): returns (w_child, psi) on
+    the child plan's lattice; r_s None selects the library's default (two
+    parent cells)."""
+    if variant not in REFINE_VARIANTS:
+        raise ValueError(f"variant must be one of {sorted(REFINE_VARIANTS)}")
+    w_parent = parent._need(w_parent, parent._real_shape(), parent.real_dtype, "w_parent")
+    w_child = child._need(w_child, child._real_shape(), child.real_dtype, "w_child")
+    psi = child._need(psi, (3,) + child._real_shape(), child.real_dtype, "psi")
+    if work is None:
+        work = child.workspace()
+    _check(lib().gg_increase_resolution(parent._h, child._h, _ptr(w_parent), REFINE_VARIANTS[variant], int(seed),
+                                        int(stream_id), 0.0 if r_s is None else float(r_s), _ptr(w_child), _ptr(psi),
+                                        _ptr(work), _stream()))
     return w_child, psi
 
 

@@ -755,6 +755,54 @@ gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const
     return interpolate_add_step(n_src, n_src / a, n_dst / a, origin, n_dst, dtype, src, dst, stream);
 }
 
+int64_t gg_cutoff_n2(double box, double r_s) {
+    if (!(box > 0) || !(r_s > 0) || !std::isfinite(box) || !std::isfinite(r_s)) return -1;
+    const double t = box / (2.0 * 3.14159265358979323846 * r_s);
+    const double c = std::ceil(t * t);
+    return c < 9.0e18 ? (int64_t)c : INT64_MAX;
+}
+
+gg_status gg_increase_resolution(const gg_plan* parent, const gg_plan* child, const void* w_parent, gg_refine variant,
+                                 uint64_t seed, uint32_t stream_id, double r_s, void* w_child, void* psi, void* work,
+                                 void* stream) {
+    if (!parent || !child || !w_parent || !w_child || !psi || !work)
+        return fail(GG_ERR_INVALID_ARG, "null argument to gg_increase_resolution");
+    if (parent->dtype != child->dtype) return fail(GG_ERR_INVALID_ARG, "parent and child plans must share the dtype");
+    if (parent->box != child->box) return fail(GG_ERR_INVALID_ARG, "parent and child plans must cover the same box");
+    int nl = 0, nh = 0;
+    gg::refine_sizes((int)variant, nl, nh);
+    if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
+    if (parent->n % nl || parent->n / nl * nh != child->n)
+        return fail(GG_ERR_INVALID_ARG, "the child lattice must have n_parent N_H / N_L cells per side");
+    if (!(r_s >= 0) || !std::isfinite(r_s)) return fail(GG_ERR_INVALID_ARG, "r_s must be >= 0 (0: two parent cells)");
+    if (!aligned(w_parent) || !aligned(w_child) || !aligned(psi) || !aligned(work))
+        return fail(GG_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    const size_t es = elem_size(parent->dtype);
+    const size_t np3 = (size_t)parent->n * parent->n * parent->n;
+    const size_t nc3 = (size_t)child->n * child->n * child->n;
+    const size_t wb = gg_workspace_bytes(child);
+    // the parent's large-scale fields, then the parent's transform workspace,
+    // both inside the child's workspace (free once Eq. 4 is done)
+    const size_t large_bytes = (3 * es * np3 + 255) & ~(size_t)255;
+    if (large_bytes + gg_workspace_bytes(parent) > wb)
+        return fail(GG_ERR_INTERNAL, "child workspace cannot hold the parent's fields");
+    if (overlap(w_parent, es * np3, w_child, es * nc3) || overlap(w_parent, es * np3, psi, 3 * es * nc3) ||
+        overlap(w_parent, es * np3, work, wb) || overlap(w_child, es * nc3, psi, 3 * es * nc3) ||
+        overlap(w_child, es * nc3, work, wb) || overlap(psi, 3 * es * nc3, work, wb))
+        return fail(GG_ERR_INVALID_ARG, "w_parent, w_child, psi and work must not overlap");
+    gg_status st = check_device(parent);
+    if (st == GG_OK) st = check_device(child);
+    if (st != GG_OK) return st;
+    const int64_t cut = gg_cutoff_n2(parent->box, r_s > 0 ? r_s : 2.0 * parent->cell);
+    void* large = work;
+    void* pwork = static_cast<char*>(work) + large_bytes;
+    st = gg_refine_noise(parent->n, parent->dtype, variant, w_parent, seed, stream_id, w_child, stream);
+    if (st == GG_OK) st = gg_make_displacements(child, w_child, cut, 0, 0, psi, work, stream);
+    if (st == GG_OK) st = gg_make_displacements(parent, w_parent, 0, cut, 1, large, pwork, stream);
+    if (st == GG_OK) st = gg_interpolate_add(parent->n, child->n, parent->dtype, large, psi, stream);
+    return st;
+}
+
 gg_status gg_lowpass(const gg_plan* pc, const void* field, int64_t n2_max, int32_t cic_deconvolve, void* out, void* work,
                      void* stream) {
     if (!pc || !field || !out || !work) return fail(GG_ERR_INVALID_ARG, "null argument to gg_lowpass");
@@ -999,12 +1047,6 @@ void zoom_free(gg_zoom* z) {
     delete z;
 }
 
-// n^2 bound of the top hat f(k r_s) = [k r_s < 1] on a box of side L
-int64_t zoom_cut(double box, double r_s) {
-    const double t = box / (2.0 * 3.14159265358979323846 * r_s);
-    return (int64_t)std::ceil(t * t);
-}
-
 }  // namespace
 
 gg_status gg_zoom_create(gg_zoom** out, const gg_zoom_desc* d, const gg_cosmo* cosmo, gg_dtype dtype) {
@@ -1101,16 +1143,16 @@ gg_status zoom_sequence(gg_zoom* z, uint64_t seed, void* const* w, void* const* 
         const double r_s = 2.0 * z->cell[l - 1];
         GG_Z(gg_refine_noise_region(np, d.origin[l], n / 2, z->dtype, (gg_refine)d.variant, w[l - 1], seed, (uint32_t)l,
                                     w[l], stream))
-        GG_Z(gg_make_displacements(z->plans[l], w[l], zoom_cut(z->box[l], r_s), 0, 0, psi[l], work, stream))
+        GG_Z(gg_make_displacements(z->plans[l], w[l], gg_cutoff_n2(z->box[l], r_s), 0, 0, psi[l], work, stream))
         const size_t rp = es * (size_t)np * np * np;
         if (l == 1) {
             // the base displacements are the filtered base noise, so Eq. 5 of them
             // is that filter on the large-scale window: one fused pass sequence
             // over the base noise instead of three transform round trips
-            GG_Z(gg_make_displacements(z->plans[0], w[0], 0, zoom_cut(z->box[0], r_s), 1, tmp, work, stream))
+            GG_Z(gg_make_displacements(z->plans[0], w[0], 0, gg_cutoff_n2(z->box[0], r_s), 1, tmp, work, stream))
         } else {
             for (int j = 0; j < 3; ++j)
-                GG_Z(gg_lowpass(z->plans[l - 1], static_cast<char*>(psi[l - 1]) + j * rp, zoom_cut(z->box[l - 1], r_s),
+                GG_Z(gg_lowpass(z->plans[l - 1], static_cast<char*>(psi[l - 1]) + j * rp, gg_cutoff_n2(z->box[l - 1], r_s),
                                 1, static_cast<char*>(tmp) + j * rp, work, stream))
         }
         GG_Z(gg_interpolate_add_at(np, 2, d.origin[l], n, z->dtype, tmp, psi[l], stream))

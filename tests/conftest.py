@@ -20,3 +20,11 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "slow" in item.keywords:
             item.add_marker(skip)
+
+
+def pytest_terminal_summary(terminalreporter):
+    from tests.gpu_util import REPORT
+    if REPORT:
+        terminalreporter.section("measured")
+        for line in REPORT:
+            terminalreporter.write_line(line)

@@ -14,6 +14,16 @@ def say(*args):
     sys.stdout.flush()
 
 
+# measured figures that the session summary prints (tests/conftest.py), so
+# they show in a quiet run's output as well
+REPORT = []
+
+
+def report(line):
+    REPORT.append(line)
+    say(line)
+
+
 def rel_rms(got, want):
     got = np.asarray(got, dtype=np.complex128 if np.iscomplexobj(got) else np.float64)
     want = np.asarray(want, dtype=got.dtype)

@@ -7,6 +7,7 @@ import re
 import subprocess
 import tempfile
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -113,3 +114,20 @@ def test_null_arguments_rejected(lib):
     assert lib.gg_plan_query(None, None) == 1
     assert lib.gg_timing_enable(None, 1) == 1
     assert lib.gg_plan_destroy(None) == 0
+
+
+@pytest.mark.parametrize("n,box,r_s", [(32, 100.0, 2 * 100.0 / 16), (64, 300.0, 2 * 300.0 / 32), (48, 40.0, 0.8),
+                                       (32, 2 * 3.14159265358979323846 * 3.0, 1.0)])
+def test_cutoff_n2_selects_the_oracle_large_scale_window(lib, n, box, r_s):
+    # host-only call: the modes with n^2 < cutoff are exactly those the
+    # oracle's top hat f(k r_s) = [k r_s < 1] keeps (Eq. 4-5)
+    from oracle import pipeline, refine
+    cut = lib.gg_cutoff_n2(box, r_s)
+    s = pipeline.signed_index(n)
+    n2 = s.reshape(n, 1, 1) ** 2 + s.reshape(1, n, 1) ** 2 + np.arange(n // 2 + 1).reshape(1, 1, -1) ** 2
+    assert np.array_equal(n2 < cut, refine.mode_window(n, box, r_s, "large") > 0)
+    assert lib.gg_cutoff_n2(0.0, 1.0) == -1 and lib.gg_cutoff_n2(100.0, float("nan")) == -1
+
+
+def test_increase_resolution_validates_before_touching_the_gpu(lib):
+    assert lib.gg_increase_resolution(None, None, None, 2, 0, 1, 0.0, None, None, None, None) == 1

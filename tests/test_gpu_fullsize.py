@@ -1,10 +1,10 @@
 """Parity at the measured size: the 1024^3 lattice (box 2000 Mpc/h) in the
 launch configuration bench.py times (fused gg_make_ic, pipelined passes).
 
-Default (fast): the float path against the double path over the whole grid,
-exact mean removal, positions within one float32 ulp at the box scale.
-Opt-in (GG_SLOW=1): both paths against the full FP64 oracle, on the whole grid
-and on a periodic 128^3 sub-box.
+The float path against the double path over the whole grid, exact mean
+removal, positions within one float32 ulp at the box scale; the fused path
+against the stand-alone calls; both paths against the full FP64 oracle, on the
+whole grid and on a periodic 128^3 sub-box (about two minutes on the host).
 """
 import os
 
@@ -14,7 +14,7 @@ import torch
 
 import paper_2511_10353_amd as gg
 from tests import inputs
-from tests.gpu_util import say
+from tests.gpu_util import report, say
 
 pytestmark = pytest.mark.gpu
 
@@ -141,14 +141,33 @@ def _oracle_noise(n, seed, dtype, workers, slabs=16):
     return out
 
 
-@pytest.mark.slow
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def test_1024_against_fp64_oracle():
+    # The headline lattice against the FP64 oracle (Eq. 1-3): both GPU paths,
+    # on the whole grid and on a periodic 128^3 sub-box.  The oracle's float
+    # noise is its binary64 noise rounded once (its definition), so the
+    # binary64 field is computed once.  Stage times of the oracle are printed
+    # as the CPU reference at this size.
+    import time
     from oracle import cosmology as ocosmo
     from oracle import pipeline as opipe
     workers = min(16, os.cpu_count() or 1)
     c = ocosmo.Cosmology()
     origin = inputs.subbox_origin(N, 42)
     idx = [np.arange(o, o + 128) % N for o in origin]
+    say(f"[1024 oracle] host: {_cpu_model()}, os.cpu_count() = {os.cpu_count()}, workers = {workers}")
+    t0 = time.perf_counter()
+    w64 = _oracle_noise(N, SEED, np.float64, workers)
+    t_noise = time.perf_counter() - t0
     results = {}
     for dtype in ("f64", "f32"):
         say(f"[1024 oracle] GPU {dtype}")
@@ -156,14 +175,19 @@ def test_1024_against_fp64_oracle():
         _, _, psi = p.make_ic(SEED, want_psi=True)
         torch.cuda.synchronize()
         p.close()
-        say(f"[1024 oracle] oracle noise {dtype} ({workers} threads)")
-        w = _oracle_noise(N, SEED, np.float32 if dtype == "f32" else np.float64, workers)
-        w_hat = opipe.forward(w.astype(np.float64), workers=workers)
+        w = w64 if dtype == "f64" else w64.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        w_hat = opipe.forward(w, workers=workers)
+        t_fwd = time.perf_counter() - t0
         del w
+        t0 = time.perf_counter()
         d_hat = opipe.density_spectrum(w_hat, N, BOX, c)
         del w_hat
+        t_inv = 0.0
         for j in range(3):
+            t1 = time.perf_counter()
             want = opipe.inverse(opipe.displacement_spectrum(d_hat, N, BOX, j), N, workers=workers)
+            t_inv += time.perf_counter() - t1
             got = psi[j].cpu().numpy().astype(np.float64)
             full = float(np.linalg.norm(got - want) / np.linalg.norm(want))
             sb = np.ix_(*idx)
@@ -171,8 +195,55 @@ def test_1024_against_fp64_oracle():
             results[(dtype, j)] = (full, sub)
             say(f"[1024 oracle] {dtype} j={j} rel_rms full grid {full:.3e}  128^3 sub-box at {origin} {sub:.3e}")
             del want, got
+        if dtype == "f64":
+            total = t_noise + t_fwd + t_inv
+            report(f"FP64 oracle at 1024^3 on {_cpu_model()} ({workers} threads): noise {t_noise:.1f} s, forward r2c "
+                   f"{t_fwd:.1f} s, filter + 3 inverse c2r {t_inv:.1f} s; {N ** 3 / total:.3e} cells/s without the "
+                   f"particle step")
         del psi, d_hat
         torch.cuda.empty_cache()
+    del w64
+    for dtype in ("f64", "f32"):
+        full = max(results[(dtype, j)][0] for j in range(3))
+        sub = max(results[(dtype, j)][1] for j in range(3))
+        report(f"1024^3 / 2000 Mpc/h {dtype} path vs FP64 oracle, psi rel_rms (worst component): full grid "
+               f"{full:.3e}, 128^3 sub-box at {origin} {sub:.3e} (bar {1e-12 if dtype == 'f64' else 2e-6:g})")
     for (dtype, j), (full, sub) in results.items():
         bar = 1e-12 if dtype == "f64" else 2e-6
         assert full < bar and sub < bar
+
+
+def test_fused_equals_standalone_chain_at_1024():
+    # the fused path (blocked spectrum rows, in-wave exchanges, persistent
+    # passes) against the stand-alone calls (public half-spectrum layout, plain
+    # rows, their own kernels) over the whole 1024^3 float grid
+    say("[1024] fused make_ic vs gg_noise + gg_fft3d + gg_filter + 3 gg_fft3d + gg_zeldovich, FP32")
+    p = gg.Plan(N, BOX, gg.Cosmo(), dtype="f32")
+    pos, vel, psi = p.make_ic(SEED, want_psi=True)
+    torch.cuda.synchronize()
+    w = p.noise(SEED)
+    spec = p.fft3d(w, 1)
+    del w
+    psi_spec = p.filter(spec)
+    del spec
+    work = p.workspace()
+    psi2 = torch.empty_like(psi)
+    for j in range(3):
+        psi2[j] = p.fft3d(psi_spec[j].contiguous(), -1, work=work)
+    del psi_spec, work
+    pos2, vel2 = p.zeldovich(psi2)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for j in range(3):
+        e = _rel_rms_t(psi[j], psi2[j])
+        ev = _rel_rms_t(vel[j], vel2[j])
+        d = (pos[j].double() - pos2[j].double()).abs()
+        dper = float(torch.minimum(d, BOX - d).max())
+        say(f"[1024] j={j} fused vs stand-alone: psi rel_rms {e:.3e}  vel {ev:.3e}  max |dpos| {dper:.3e}")
+        worst = max(worst, e)
+        assert e < 1e-6 and ev < 1e-6
+        assert dper <= float(np.spacing(np.float32(BOX)))
+    report(f"1024^3 FP32 fused make_ic vs stand-alone calls: psi rel_rms {worst:.3e} (worst component)")
+    del pos, vel, psi, pos2, vel2, psi2
+    p.close()
+    torch.cuda.empty_cache()

@@ -151,3 +151,28 @@ def test_three_halves_resolution_increase_against_oracle(dtype):
         assert err < TOL[dtype]
     pos, vel = child.zeldovich(psi)
     assert float(pos.min()) >= 0.0 and float(pos.max()) < box
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("variant,r_cells", [("hr", 2.0), ("linear", 3.5), ("sine", 1.25)])
+def test_increase_resolution_variants_and_cutoffs(dtype, variant, r_cells):
+    # gg_increase_resolution with other bases and an explicit cutoff scale
+    # (in parent cells) against the oracle's Eq. 4-5 combination
+    n_p = 32
+    box = 6.25 * n_p
+    parent = _plan(n_p, box, dtype)
+    child = _plan(2 * n_p, box, dtype)
+    c = oracle_cosmo(parent.cosmo)
+    wp = parent.noise(11)
+    r_s = r_cells * box / n_p
+    w_child, psi = gg.increase_resolution(parent, child, wp, variant, seed=5, stream_id=2, r_s=r_s)
+    wp64 = wp.cpu().numpy().astype(np.float64)
+    wc_want = oref.refine(wp64, variant, seed=5, stream=2)
+    wc = w_child.cpu().numpy().astype(np.float64)
+    assert np.abs(wc - wc_want).max() < (1e-14 if dtype == "f64" else 2e-7 * np.abs(wc_want).max())
+    want = oref.combine(wp64, wc, box, c, r_s)
+    got = psi.cpu().numpy()
+    for j in range(3):
+        err = rel_rms(got[j], want[j])
+        say(f"[increase] {dtype} {variant} r_s={r_cells} cells comp {j} rel rms {err:.3e}")
+        assert err < TOL[dtype]
