@@ -61,6 +61,35 @@ def build(verbose=True, lib=LIB, build_dir=BUILD, defines=()):
     return lib
 
 
+def build_host_sanitized(build_dir=os.path.join(ROOT, "_build_san")):
+    """libgg with its host code (gg_api.hip: validation, plans, dispatch)
+    built under AddressSanitizer and UndefinedBehaviorSanitizer; the device
+    code is built as usual (GPU sanitizers are not used).  The kernel-only
+    sources are taken from the regular build.  Returns the library's path;
+    load it with the clang ASan runtime preloaded (see
+    tests/test_abi_sanitized.py)."""
+    os.makedirs(build_dir, exist_ok=True)
+    if not all(os.path.exists(os.path.join(BUILD, os.path.basename(s) + ".o"))
+               for s in glob.glob(os.path.join(CSRC, "*.hip"))):
+        build(verbose=False)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    api = os.path.join(CSRC, "gg_api.hip")
+    obj = os.path.join(build_dir, "gg_api.hip.o")
+    flags = [f for f in CFLAGS if f != "-O3"] + ["-O1", "-g"]
+    res = subprocess.run([HIPCC, *flags, *san, "-c", api, "-o", obj], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc (host sanitizers) failed:\n{res.stdout}\n{res.stderr}")
+    objs = [obj] + [os.path.join(BUILD, os.path.basename(s) + ".o")
+                    for s in sorted(glob.glob(os.path.join(CSRC, "*.hip"))) if os.path.basename(s) != "gg_api.hip"]
+    lib = os.path.join(build_dir, "libgg_san.so")
+    res = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib, *objs, *san, "-shared-libasan",
+                          "-Wl,-rpath,/opt/rocm/lib"], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link (host sanitizers) failed:\n{res.stdout}\n{res.stderr}")
+    return lib
+
+
 if __name__ == "__main__":
     build()
     sys.exit(0)

@@ -73,6 +73,22 @@ namespace {
 
 bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
+// The integer a caller passed for an enum parameter.  A C caller may pass any
+// int; in C++ reading an enum object that holds a value outside the
+// enumeration's range is undefined, so validation reads the representation.
+template <typename E>
+int32_t enum_bits(const E& e) {
+    static_assert(sizeof(E) == sizeof(int32_t), "enums of the ABI are int-sized");
+    int32_t v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
+bool valid_dtype(const gg_dtype& d) {
+    const int32_t v = enum_bits(d);
+    return v == GG_F32 || v == GG_F64;
+}
+
 // launch context of the fused path for plan p on the caller's stream
 gg::ExecCtx fused_ctx(gg_plan* p, void* stream) {
     gg::ExecCtx x;
@@ -188,7 +204,7 @@ size_t gg_workspace_bytes(const gg_plan* p) {
 gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cosmo, gg_dtype dtype) {
     g_last_error.clear();
     if (!out || !grid || !cosmo) return fail(GG_ERR_INVALID_ARG, "null argument to gg_plan_create");
-    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "dtype must be GG_F32 or GG_F64");
+    if (!valid_dtype(dtype)) return fail(GG_ERR_INVALID_ARG, "dtype must be GG_F32 or GG_F64");
     if (!gg::supported_n(grid->n))
         return fail(GG_ERR_UNSUPPORTED_SIZE,
                     "N must be a power of two in [8, 1024] or one of 96, 160, 192, got " + std::to_string(grid->n));
@@ -638,9 +654,9 @@ gg_status gg_refine_noise_region(int32_t n_parent, const int32_t origin[3], int3
                                  gg_refine variant, const void* parent, uint64_t seed, uint32_t stream_id, void* child,
                                  void* stream) {
     if (!parent || !child || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_refine_noise_region");
-    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    if (!valid_dtype(dtype)) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
     int nl = 0, nh = 0;
-    gg::refine_sizes((int)variant, nl, nh);
+    gg::refine_sizes(enum_bits(variant), nl, nh);
     if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
     if (n_parent < 1 || n_parent > 4096) return fail(GG_ERR_INVALID_ARG, "n_parent must be in [1, 4096]");
     if (count < nl || count % nl || count > n_parent)
@@ -664,8 +680,9 @@ gg_status gg_refine_noise_region(int32_t n_parent, const int32_t origin[3], int3
 
 gg_status gg_refine_noise(int32_t n_parent, gg_dtype dtype, gg_refine variant, const void* parent, uint64_t seed,
                           uint32_t stream_id, void* child, void* stream) {
+    if (!valid_dtype(dtype)) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
     int nl = 0, nh = 0;
-    gg::refine_sizes((int)variant, nl, nh);
+    gg::refine_sizes(enum_bits(variant), nl, nh);
     if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
     if (n_parent < nl || n_parent % nl) return fail(GG_ERR_INVALID_ARG, "n_parent must be a positive multiple of N_L");
     const int32_t origin[3] = {0, 0, 0};
@@ -734,7 +751,7 @@ gg_status interpolate_add_step(int32_t n_src, int32_t num, int32_t den, const in
 gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t origin[3], int32_t n_dst, gg_dtype dtype,
                                 const void* src, void* dst, void* stream) {
     if (!src || !dst || !origin) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add_at");
-    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    if (!valid_dtype(dtype)) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
     if (n_src < 1 || n_src > 4096 || n_dst < 1 || n_dst > 4096 || ratio < 1 || ratio > 64)
         return fail(GG_ERR_INVALID_ARG, "sizes in [1, 4096], ratio in [1, 64]");
     return interpolate_add_step(n_src, 1, ratio, origin, n_dst, dtype, src, dst, stream);
@@ -742,7 +759,7 @@ gg_status gg_interpolate_add_at(int32_t n_src, int32_t ratio, const int32_t orig
 
 gg_status gg_interpolate_add(int32_t n_src, int32_t n_dst, gg_dtype dtype, const void* src, void* dst, void* stream) {
     if (!src || !dst) return fail(GG_ERR_INVALID_ARG, "null argument to gg_interpolate_add");
-    if (dtype != GG_F32 && dtype != GG_F64) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
+    if (!valid_dtype(dtype)) return fail(GG_ERR_INVALID_ARG, "unknown dtype");
     if (n_src < 1 || n_src > 4096 || n_dst < n_src || n_dst > 4096)
         return fail(GG_ERR_INVALID_ARG, "sizes must satisfy 1 <= n_src <= n_dst <= 4096");
     int32_t a = n_src, b = n_dst;
@@ -770,7 +787,7 @@ gg_status gg_increase_resolution(const gg_plan* parent, const gg_plan* child, co
     if (parent->dtype != child->dtype) return fail(GG_ERR_INVALID_ARG, "parent and child plans must share the dtype");
     if (parent->box != child->box) return fail(GG_ERR_INVALID_ARG, "parent and child plans must cover the same box");
     int nl = 0, nh = 0;
-    gg::refine_sizes((int)variant, nl, nh);
+    gg::refine_sizes(enum_bits(variant), nl, nh);
     if (nl == 0) return fail(GG_ERR_INVALID_ARG, "unknown refinement variant");
     if (parent->n % nl || parent->n / nl * nh != child->n)
         return fail(GG_ERR_INVALID_ARG, "the child lattice must have n_parent N_H / N_L cells per side");
@@ -1051,6 +1068,7 @@ void zoom_free(gg_zoom* z) {
 
 gg_status gg_zoom_create(gg_zoom** out, const gg_zoom_desc* d, const gg_cosmo* cosmo, gg_dtype dtype) {
     if (!out || !d || !cosmo) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zoom_create");
+    if (!valid_dtype(dtype)) return fail(GG_ERR_INVALID_ARG, "dtype must be GG_F32 or GG_F64");
     if (d->levels < 1 || d->levels > GG_ZOOM_MAX_LEVELS) return fail(GG_ERR_INVALID_ARG, "levels must be in [1, 8]");
     if (!(d->box > 0) || !std::isfinite(d->box)) return fail(GG_ERR_INVALID_ARG, "box must be > 0");
     int nl = 0, nh = 0;

@@ -131,3 +131,16 @@ def test_cutoff_n2_selects_the_oracle_large_scale_window(lib, n, box, r_s):
 
 def test_increase_resolution_validates_before_touching_the_gpu(lib):
     assert lib.gg_increase_resolution(None, None, None, 2, 0, 1, 0.0, None, None, None, None) == 1
+
+
+def test_out_of_range_enums_rejected(lib):
+    # a C caller may pass any int for an enum parameter: rejected, not used
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert lib.gg_refine_noise(16, 7, 2, fake, 1, 1, fake, None) == 1
+    assert lib.gg_refine_noise(16, 0, 9, fake, 1, 1, fake, None) == 1
+    origin = (ctypes.c_int32 * 3)(0, 0, 0)
+    assert lib.gg_refine_noise_region(16, origin, 8, 2, 2, fake, 1, 1, fake, None) == 1
+    assert lib.gg_interpolate_add(8, 16, 5, fake, fake, None) == 1
+    assert lib.gg_interpolate_add_at(8, 2, origin, 8, -1, fake, fake, None) == 1
+    st, msg = _create(lib, dtype=-3)
+    assert st == 1 and "dtype" in msg
