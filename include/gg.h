@@ -173,6 +173,22 @@ gg_status gg_zeldovich(const gg_plan* plan, const void* psi, float* pos, float* 
 gg_status gg_make_ic(const gg_plan* plan, uint64_t seed, float* pos, float* vel, void* psi_opt, void* work,
                      void* stream);
 
+/* gg_make_ic without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a static device array of
+ * GG_NOALLOC_SCRATCH_BYTES (48 MiB) that the library holds on each device it
+ * runs on until the process ends; its address is looked up once per device
+ * by gg_plan_create.  Lattices whose gg_workspace_bytes exceeds it (float
+ * plans above 160^3, double plans above 128^3) are rejected with
+ * GG_ERR_UNSUPPORTED_SIZE.  Allocates nothing.  Every call on a device shares
+ * that device's array: calls that overlap in time on one device (two host
+ * threads, or two streams without ordering) race and give undefined
+ * results.  No state is kept between calls: every workspace byte a call reads
+ * is written earlier in the same call.  Arguments and results otherwise as
+ * for gg_make_ic. */
+#define GG_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+gg_status gg_make_ic_noalloc(const gg_plan* plan, uint64_t seed, float* pos, float* vel, void* psi_opt, void* stream);
+
 /* The same path with the white noise given instead of generated: w is R in the
  * plan's dtype.  amp_scale multiplies the displacements (amp_scale^2 scales
  * the spectrum amplitude A; 1 keeps the plan's).  pos and vel may both be NULL

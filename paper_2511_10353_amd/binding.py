@@ -80,6 +80,7 @@ _SIGS = {
     "gg_filter": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "gg_zeldovich": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "gg_make_ic": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP]),
+    "gg_make_ic_noalloc": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP]),
     "gg_make_ic_from_noise": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
     "gg_make_ic_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP]),
     "gg_make_density": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP]),
@@ -239,6 +240,16 @@ class Plan:
         elif work.numel() * work.element_size() < self.workspace_bytes or not work.is_cuda:
             raise ValueError("work buffer too small")
         _check(lib().gg_make_ic(self._h, int(seed), _ptr(pos), _ptr(vel), _ptr(psi), _ptr(work), _stream()))
+        return (pos, vel, psi) if psi is not None else (pos, vel)
+
+    def make_ic_noalloc(self, seed, pos=None, vel=None, psi=None, want_psi=False):
+        """gg_make_ic_noalloc: the fused path on the library's static workspace
+        (no workspace argument; lattices up to the library's scratch size)."""
+        pos = self._need(pos, (3,) + self._real_shape(), torch.float32, "pos")
+        vel = self._need(vel, (3,) + self._real_shape(), torch.float32, "vel")
+        if want_psi or psi is not None:
+            psi = self._need(psi, (3,) + self._real_shape(), self.real_dtype, "psi")
+        _check(lib().gg_make_ic_noalloc(self._h, int(seed), _ptr(pos), _ptr(vel), _ptr(psi), _stream()))
         return (pos, vel, psi) if psi is not None else (pos, vel)
 
     def make_ic_from_noise(self, w, amp_scale=1.0, pos=None, vel=None, psi=None, work=None, particles=True,

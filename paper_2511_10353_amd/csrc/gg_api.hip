@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -87,6 +88,33 @@ int32_t enum_bits(const E& e) {
 bool valid_dtype(const gg_dtype& d) {
     const int32_t v = enum_bits(d);
     return v == GG_F32 || v == GG_F64;
+}
+
+// Workspace of gg_make_ic_noalloc: one static array per device, found once
+// per device (gg_plan_create, with the plan's device current) through
+// hipGetSymbolAddress.  Host code uses only the recorded device address;
+// the array's own name is a host-side stand-in that no kernel may receive.
+constexpr size_t kScratchBytes = gg::kNoallocScratchBytes;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gg_status scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(GG_ERR_INTERNAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return GG_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = ptr;
+    return GG_OK;
+}
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 // launch context of the fused path for plan p on the caller's stream
@@ -232,6 +260,13 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     if (e != hipSuccess) {
         delete p;
         return fail_hip(e, "hipGetDevice / compute unit count");
+    }
+    {
+        const gg_status ss = scratch_setup(p->device);
+        if (ss != GG_OK) {
+            delete p;
+            return ss;
+        }
     }
     p->cus = cus > 0 ? cus : 256;
     // GG_CUS (tests): size the persistent passes' grids for fewer compute units
@@ -504,6 +539,21 @@ gg_status gg_make_ic(const gg_plan* pc, uint64_t seed, float* pos, float* vel, v
         e = gg::Ops<float>::make_ic(view<float>(p), seed, pos, vel, static_cast<float*>(psi_opt),
                                     static_cast<gg::cx<float>*>(work), x);
     return e == hipSuccess ? GG_OK : fail_hip(e, "make_ic launch");
+}
+
+gg_status gg_make_ic_noalloc(const gg_plan* pc, uint64_t seed, float* pos, float* vel, void* psi_opt, void* stream) {
+    if (!pc || !pos || !vel) return fail(GG_ERR_INVALID_ARG, "null argument to gg_make_ic_noalloc");
+    const size_t wb = gg_workspace_bytes(pc);
+    if (wb > kScratchBytes)
+        return fail(GG_ERR_UNSUPPORTED_SIZE,
+                    "gg_make_ic_noalloc: this lattice needs " + std::to_string(wb) + " bytes of workspace, the static "
+                    "scratch holds " + std::to_string(kScratchBytes) + " (float lattices up to 160^3, double up to "
+                    "128^3); use gg_make_ic with a workspace");
+    gg_status st = check_device(pc);
+    if (st != GG_OK) return st;
+    void* ws = scratch_ptr(pc->device);
+    if (!ws) return fail(GG_ERR_INTERNAL, "no scratch address recorded for the plan's device");
+    return gg_make_ic(pc, seed, pos, vel, psi_opt, ws, stream);
 }
 
 gg_status gg_make_ic_from_noise(const gg_plan* pc, const void* w, double amp_scale, float* pos, float* vel,

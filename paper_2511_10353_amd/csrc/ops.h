@@ -103,6 +103,9 @@ struct Ops {
     static size_t inverse_work_bytes(int n) { return (size_t)n * n * (n / 2 + 1) * sizeof(cx<T>); }
 };
 
+// Bytes of the static workspace behind gg_make_ic_noalloc (per device).
+constexpr size_t kNoallocScratchBytes = (size_t)48 << 20;
+
 // (N_L, N_H) of a refinement variant, or (0, 0) if unknown
 void refine_sizes(int variant, int& nl, int& nh);
 
