@@ -130,11 +130,11 @@ def time_path(gg, torch, n, box, dtype, steps, warmup, seed=42, autotune=True, f
             "autotune": [dict(t, ms=round(t["ms"], 3)) for t in tuning]}
 
 
-def time_zoom(gg, torch, steps, seed=42):
+def time_zoom(gg, torch, steps, seed=42, autotune=True):
     """The nested zoom hierarchy: base 256^3 over 300 Mpc/h plus 192^3, 160^3,
     96^3 levels at 2x, 4x, 8x (origins from PCG64 seed 42), FP32; one step =
     every level's noise, displacements and particles; eager launches and one
-    replayed HIP graph."""
+    replayed HIP graph, after the per-level tile autotuner (unless disabled)."""
     import numpy as np
     n0, box0, sizes = 256, 300.0, [192, 160, 96]
     rng = np.random.default_rng(42)
@@ -149,6 +149,11 @@ def time_zoom(gg, torch, steps, seed=42):
     z = gg.Zoom(n0, box0, sizes, origins, dtype="f32")
     s = torch.cuda.Stream()
     out = {"workload": "zoom: 256^3 / 300 Mpc/h + 192^3, 160^3, 96^3 at 2x, 4x, 8x, FP32", "origins": origins}
+    if autotune:
+        with torch.cuda.stream(s):
+            table = z.autotune(seed=seed, reps=5)
+        torch.cuda.synchronize()
+        out["autotune"] = [dict(e, ms=round(e["ms"], 4)) for e in table]
     cells = sum(n ** 3 for n in [n0] + sizes)
     with torch.cuda.stream(s):
         for mode in ("eager", "graph"):
@@ -335,6 +340,8 @@ def main():
     ap.add_argument("--tuning", default=None, metavar="CHUNKS,P1_LINES,Z_LINES",
                     help="fixed launch configuration of the FP32 path instead of the autotuner "
                          "(the FP64 path then keeps its built-in one)")
+    ap.add_argument("--zoom-only", action="store_true",
+                    help="only time the zoom hierarchy (for a kernel trace of that workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 4 GiB streaming copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -350,6 +357,10 @@ def main():
         print(json.dumps(calibrate_copy(torch)), flush=True)
         return 0
     gg.lib()
+    if args.zoom_only:
+        print(json.dumps({"zoom": time_zoom(gg, torch, max(args.steps // 2, 1), autotune=not args.no_autotune)}),
+              flush=True)
+        return 0
     copy_gbs = copy_peak(torch)
     fixed = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
     f32 = time_path(gg, torch, args.n, args.box, "f32", args.steps, args.warmup, autotune=not args.no_autotune,
@@ -401,7 +412,7 @@ def main():
     out["config"]["tuning"] = f32["tuning"]
     out["autotune"] = f32["autotune"]
     if not args.no_zoom:
-        out["zoom"] = time_zoom(gg, torch, max(args.steps // 2, 1))
+        out["zoom"] = time_zoom(gg, torch, max(args.steps // 2, 1), autotune=not args.no_autotune)
     if not args.no_adjoint:
         out["adjoint"] = time_adjoint(gg, torch, args.n, args.box, "f32", max(args.steps // 2, 1), 1)
     if not args.no_extras and args.n >= 16:

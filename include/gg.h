@@ -372,14 +372,39 @@ size_t gg_zoom_workspace_bytes(const gg_zoom* zoom);
 /* Level geometry: sub-box side, cell size and origin in the base box (Mpc/h). */
 gg_status gg_zoom_query(const gg_zoom* zoom, int32_t level, double* box, double* cell, double origin[3]);
 
-/* Runs the whole hierarchy on `stream`.  w[l] (R of level l), psi[l] (3 R),
- * pos[l] and vel[l] (3 n[l]^3 floats) are host arrays of device pointers, one
- * per level; work: gg_zoom_workspace_bytes.  With use_graph set, the launch
- * sequence is captured into a HIP graph on the first call (stream must not be
- * NULL) and replayed as one graph launch while seed and pointers stay the
- * same (captured again otherwise).  Calls on one zoom must not overlap. */
+/* Runs the whole hierarchy.  w[l] (R of level l), psi[l] (3 R), pos[l] and
+ * vel[l] (3 n[l]^3 floats) are host arrays of device pointers, one per level;
+ * work: gg_zoom_workspace_bytes.  The work is spread over `stream` and two
+ * streams owned by the zoom object, ordered by events: the noise refinement
+ * and Eq. 4 of every level (which need only the noise) run beside the chain
+ * of Eq. 5 and CiC interpolations (each level's large scales need its
+ * parent's final displacements), and each level's particles are made as soon
+ * as its displacements are final.  The call is ordered after earlier work on
+ * `stream`; later work on `stream` starts after all of it.  With use_graph
+ * set, the schedule is captured into one HIP graph on the first call (stream
+ * must not be NULL) and replayed as one graph launch while seed and pointers
+ * stay the same (captured again otherwise).  Calls on one zoom must not
+ * overlap. */
 gg_status gg_zoom_run(gg_zoom* zoom, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
                       float* const* vel, void* work, int32_t use_graph, void* stream);
+
+/* Autotuner of the hierarchy: for each level in turn (the others kept), times
+ * gg_zoom_run (eager; one warm-up, then reps calls, HIP events on `stream`)
+ * for the tile widths of the level's first and last fused passes (the full
+ * LDS row of lines or half of it, as gg_plan_set_tuning), keeps the fastest
+ * (a later choice must win by more than 0.5 %) and reports every timing (up
+ * to `capacity` entries; *count = number timed).  Arguments of the run as for
+ * gg_zoom_run (overwritten).  A captured graph is dropped (the next graph run
+ * captures the tuned launches).  Synchronous. */
+typedef struct {
+    int32_t level;
+    int32_t p1_lines;
+    int32_t z_lines;
+    double ms;
+} gg_zoom_tune_entry;
+gg_status gg_zoom_autotune(gg_zoom* zoom, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
+                           float* const* vel, void* work, int32_t reps, gg_zoom_tune_entry* results, int32_t capacity,
+                           int32_t* count, void* stream);
 
 /* Launch configuration of the fused path: chunks (pipelined launches per pass,
  * 1 = none; 0 keeps the current value), lines per work-group of the first and

@@ -105,6 +105,8 @@ _SIGS = {
     "gg_zoom_workspace_bytes": (ctypes.c_size_t, [_VP]),
     "gg_zoom_query": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "gg_zoom_run": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    "gg_zoom_autotune": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP,
+                                        ctypes.c_int32, _VP, _VP]),
     "gg_plan_set_tuning": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "gg_plan_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, ctypes.c_int32, _VP, _VP]),
     "gg_timing_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -454,6 +456,11 @@ class _ZoomDesc(ctypes.Structure):
                 ("box", ctypes.c_double), ("variant", ctypes.c_int32)]
 
 
+class _ZoomTuneEntry(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("p1_lines", ctypes.c_int32), ("z_lines", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 class Zoom:
     """A zoom hierarchy: base lattice n0^3 over ``box`` plus nested levels of
     ``sizes`` at origins (parent cells); buffers are allocated once and reused."""
@@ -498,6 +505,17 @@ class Zoom:
         _check(lib().gg_zoom_run(self._h, int(seed), self._ptrs["w"], self._ptrs["psi"], self._ptrs["pos"],
                                  self._ptrs["vel"], _ptr(self.work), int(bool(use_graph)), _stream()))
         return self.levels
+
+    def autotune(self, seed=42, reps=5):
+        """gg_zoom_autotune: per-level tile widths, kept in the zoom; returns
+        the timings [{level, p1_lines, z_lines, ms}]."""
+        cap = 4 * len(self.ns)
+        res = (_ZoomTuneEntry * cap)()
+        count = ctypes.c_int32()
+        _check(lib().gg_zoom_autotune(self._h, int(seed), self._ptrs["w"], self._ptrs["psi"], self._ptrs["pos"],
+                                      self._ptrs["vel"], _ptr(self.work), int(reps), res, cap, ctypes.byref(count),
+                                      _stream()))
+        return [dict(level=e.level, p1_lines=e.p1_lines, z_lines=e.z_lines, ms=e.ms) for e in res[:count.value]]
 
     def close(self):
         if self._h:

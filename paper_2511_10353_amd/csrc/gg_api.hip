@@ -1097,6 +1097,18 @@ struct gg_zoom {
     std::vector<std::array<double, 3>> origin_box;  // level origin in the base box
     size_t plan_work = 0;                           // max plan workspace
     size_t tmp_bytes = 0;                           // 3 R of the largest parent
+    // the hierarchy runs as three streams: the caller's (base particles, the
+    // levels' particles), side[0] (noise refinement and Eq. 4 of every level,
+    // which depend on the noise only) and side[1] (the chain of Eq. 5 and the
+    // CiC interpolation, level by level); events order them
+    hipStream_t side[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> ev;  // kZoomEvents
+    // workspace layout (bytes from the start): the chain's transform work and
+    // the parent's filtered fields, then one transform work per level for its
+    // Eq. 4 (level 0: the base particles)
+    size_t chain_off = 0, tmp_off = 0;
+    std::vector<size_t> level_off;
+    size_t total_work = 0;
     // captured graph and the arguments it was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1106,10 +1118,22 @@ struct gg_zoom {
 
 namespace {
 
+// events per hierarchy: base noise done, Eq. 4 of level l done (8), psi of
+// level l final (8), the two side streams done (2)
+constexpr int kZoomEvents = 1 + 2 * GG_ZOOM_MAX_LEVELS + 2;
+constexpr int kEvW0 = 0;
+constexpr int kEvEq4 = 1;
+constexpr int kEvPsi = 1 + GG_ZOOM_MAX_LEVELS;
+constexpr int kEvEnd = 1 + 2 * GG_ZOOM_MAX_LEVELS;
+
 void zoom_free(gg_zoom* z) {
     if (!z) return;
     if (z->exec) hipGraphExecDestroy(z->exec);
     if (z->graph) hipGraphDestroy(z->graph);
+    for (hipEvent_t e : z->ev)
+        if (e) hipEventDestroy(e);
+    for (hipStream_t st : z->side)
+        if (st) hipStreamDestroy(st);
     for (gg_plan* p : z->plans) gg_plan_destroy(p);
     delete z;
 }
@@ -1159,13 +1183,32 @@ gg_status gg_zoom_create(gg_zoom** out, const gg_zoom_desc* d, const gg_cosmo* c
             zoom_free(z);
             return st;
         }
-        p->nchunk = 1;  // one stream: the whole hierarchy can be captured as a graph
+        p->nchunk = 1;  // no plan-owned stream: the hierarchy's own streams are the whole schedule
         z->plans.push_back(p);
         z->box.push_back(box);
         z->cell.push_back(cell);
         z->origin_box.push_back(org);
         z->plan_work = std::max(z->plan_work, gg_workspace_bytes(p));
         if (l + 1 < d->levels) z->tmp_bytes = std::max(z->tmp_bytes, 3 * es * (size_t)d->n[l] * d->n[l] * d->n[l]);
+    }
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    z->chain_off = 0;
+    z->tmp_off = up(z->plan_work);
+    size_t off = z->tmp_off + up(z->tmp_bytes);
+    for (int l = 0; l < d->levels; ++l) {
+        z->level_off.push_back(off);
+        off += up(gg_workspace_bytes(z->plans[l]));
+    }
+    z->total_work = off;
+    hipError_t e = hipSuccess;
+    for (hipStream_t& st : z->side)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    z->ev.assign(kZoomEvents, nullptr);
+    for (hipEvent_t& ev : z->ev)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        zoom_free(z);
+        return fail_hip(e, "zoom streams and events");
     }
     *out = z;
     return GG_OK;
@@ -1181,7 +1224,83 @@ gg_status gg_zoom_destroy(gg_zoom* z) {
 
 size_t gg_zoom_workspace_bytes(const gg_zoom* z) {
     if (!z) return 0;
-    return (z->plan_work + 255) / 256 * 256 + z->tmp_bytes;
+    return z->total_work;
+}
+
+gg_status gg_zoom_autotune(gg_zoom* z, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
+                           float* const* vel, void* work, int32_t reps, gg_zoom_tune_entry* results, int32_t capacity,
+                           int32_t* count, void* stream) {
+    if (!z || !count) return fail(GG_ERR_INVALID_ARG, "null argument to gg_zoom_autotune");
+    if (reps < 1 || reps > 100) return fail(GG_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) {
+        if (t0) hipEventDestroy(t0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    auto time_run = [&](double& ms_out) -> gg_status {
+        gg_status st = gg_zoom_run(z, seed, w, psi, pos, vel, work, 0, stream);  // warm-up
+        if (st != GG_OK) return st;
+        if ((e = hipEventRecord(t0, s)) != hipSuccess) return fail_hip(e, "autotune timing");
+        for (int r = 0; r < reps && st == GG_OK; ++r) st = gg_zoom_run(z, seed, w, psi, pos, vel, work, 0, stream);
+        if (st != GG_OK) return st;
+        if ((e = hipEventRecord(t1, s)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess)
+            return fail_hip(e, "autotune timing");
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) return fail_hip(e, "autotune timing");
+        ms_out = (double)ms / reps;
+        return GG_OK;
+    };
+    // one level at a time (the others at their current choice): the tile
+    // widths of its first and last fused passes, full LDS row or half; a later
+    // choice must win by the same margin as in gg_plan_autotune
+    int n = 0;
+    gg_status st = GG_OK;
+    for (int l = 0; l < z->d.levels && st == GG_OK; ++l) {
+        gg_plan* p = z->plans[l];
+        int full = 0, half = 0, p1d = 0, zd = 0;
+        if (p->dtype == GG_F64) gg::Ops<double>::tile_options(p->n, full, half, p1d, zd);
+        else gg::Ops<float>::tile_options(p->n, full, half, p1d, zd);
+        std::vector<int> lines_set{full};
+        if (half != full) lines_set.push_back(half);
+        const int keep_1 = p->p1_lines, keep_z = p->z_lines;
+        double best = 1e300;
+        int b1 = keep_1, bz = keep_z;
+        for (int l1 : lines_set) {
+            for (int lz : lines_set) {
+                p->p1_lines = l1;
+                p->z_lines = lz;
+                double ms = 0.0;
+                if ((st = time_run(ms)) != GG_OK) break;
+                if (results && n < capacity) results[n] = gg_zoom_tune_entry{l, l1, lz, ms};
+                ++n;
+                if (ms < best * (1.0 - kTuneMargin)) {
+                    best = ms;
+                    b1 = l1;
+                    bz = lz;
+                }
+            }
+            if (st != GG_OK) break;
+        }
+        p->p1_lines = st == GG_OK ? b1 : keep_1;
+        p->z_lines = st == GG_OK ? bz : keep_z;
+    }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    // a graph captured before holds the old launch shapes
+    if (z->exec) {
+        hipGraphExecDestroy(z->exec);
+        z->exec = nullptr;
+    }
+    if (z->graph) {
+        hipGraphDestroy(z->graph);
+        z->graph = nullptr;
+    }
+    if (st != GG_OK) return st;
+    *count = n;
+    return GG_OK;
 }
 
 gg_status gg_zoom_query(const gg_zoom* z, int32_t level, double* box, double* cell, double origin[3]) {
@@ -1195,38 +1314,93 @@ gg_status gg_zoom_query(const gg_zoom* z, int32_t level, double* box, double* ce
 
 namespace {
 
+// Eq. 5 of the three components of a level's displacements (3 R of plan p)
+// into out (3 R): the pruned three-field transform
+gg_status zoom_lowpass3(const gg_plan* p, const void* field, int64_t n2_max, void* out, void* work, hipStream_t s) {
+    const int hi = (int)(n2_max <= 0 || n2_max > 0x7FFFFFFF ? 0x7FFFFFFF : n2_max);
+    const hipError_t e =
+        p->dtype == GG_F64
+            ? gg::Ops<double>::lowpass3(view<double>(p), static_cast<const double*>(field), hi, 1,
+                                        static_cast<double*>(out), static_cast<gg::cx<double>*>(work), s)
+            : gg::Ops<float>::lowpass3(view<float>(p), static_cast<const float*>(field), hi, 1, static_cast<float*>(out),
+                                       static_cast<gg::cx<float>*>(work), s);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "zoom lowpass launch");
+}
+
+// Eq. 5 of the base displacements as the base filter on the large-scale
+// window (with the CiC deconvolution) applied to the base noise: psi (3 R)
+gg_status zoom_base_window(gg_plan* p, const void* w, int64_t n2_max, void* psi, void* work, hipStream_t s) {
+    const int hi = (int)(n2_max <= 0 || n2_max > 0x7FFFFFFF ? 0x7FFFFFFF : n2_max);
+    const gg::ExecCtx x = fused_ctx(p, s);
+    const hipError_t e =
+        p->dtype == GG_F64
+            ? gg::Ops<double>::windowed_displacements(view<double>(p), static_cast<const double*>(w), hi, 1,
+                                                      static_cast<double*>(psi), static_cast<gg::cx<double>*>(work), x)
+            : gg::Ops<float>::windowed_displacements(view<float>(p), static_cast<const float*>(w), hi, 1,
+                                                     static_cast<float*>(psi), static_cast<gg::cx<float>*>(work), x);
+    return e == hipSuccess ? GG_OK : fail_hip(e, "zoom window launch");
+}
+
 gg_status zoom_sequence(gg_zoom* z, uint64_t seed, void* const* w, void* const* psi, float* const* pos,
                         float* const* vel, void* work, void* stream) {
     const gg_zoom_desc& d = z->d;
     char* wk = static_cast<char*>(work);
-    void* tmp = wk + (z->plan_work + 255) / 256 * 256;
-    const size_t es = elem_size(z->dtype);
+    void* chain = wk + z->chain_off;
+    void* tmp = wk + z->tmp_off;
+    hipStream_t s0 = static_cast<hipStream_t>(stream);
+    hipStream_t s1 = z->side[0], s2 = z->side[1];
     gg_status st;
+    hipError_t e;
 #define GG_Z(expr) \
     if ((st = (expr)) != GG_OK) return st;
+#define GG_ZH(expr) \
+    if ((e = (expr)) != hipSuccess) return fail_hip(e, "zoom stream ordering");
     GG_Z(gg_noise(z->plans[0], seed, 0u, w[0], stream))
-    GG_Z(gg_make_ic_from_noise(z->plans[0], w[0], 1.0, pos[0], vel[0], psi[0], work, stream))
+    GG_ZH(hipEventRecord(z->ev[kEvW0], s0))
+    GG_ZH(hipStreamWaitEvent(s1, z->ev[kEvW0], 0))
+    GG_ZH(hipStreamWaitEvent(s2, z->ev[kEvW0], 0))
+    // side[0]: each level's noise (App. A refinement of its parent's sub-box)
+    // and its small scales (Eq. 4 on the level's own periodic sub-box)
     for (int l = 1; l < d.levels; ++l) {
         const int np = d.n[l - 1], n = d.n[l];
         const double r_s = 2.0 * z->cell[l - 1];
         GG_Z(gg_refine_noise_region(np, d.origin[l], n / 2, z->dtype, (gg_refine)d.variant, w[l - 1], seed, (uint32_t)l,
-                                    w[l], stream))
-        GG_Z(gg_make_displacements(z->plans[l], w[l], gg_cutoff_n2(z->box[l], r_s), 0, 0, psi[l], work, stream))
-        const size_t rp = es * (size_t)np * np * np;
+                                    w[l], s1))
+        GG_Z(gg_make_displacements(z->plans[l], w[l], gg_cutoff_n2(z->box[l], r_s), 0, 0, psi[l], wk + z->level_off[l],
+                                   s1))
+        GG_ZH(hipEventRecord(z->ev[kEvEq4 + l], s1))
+    }
+    // side[1]: the large scales of each level (Eq. 5 of its parent's final
+    // displacements, CiC-interpolated), which chain from level to level
+    for (int l = 1; l < d.levels; ++l) {
+        const int np = d.n[l - 1], n = d.n[l];
+        const double r_s = 2.0 * z->cell[l - 1];
         if (l == 1) {
             // the base displacements are the filtered base noise, so Eq. 5 of them
             // is that filter on the large-scale window: one fused pass sequence
             // over the base noise instead of three transform round trips
-            GG_Z(gg_make_displacements(z->plans[0], w[0], 0, gg_cutoff_n2(z->box[0], r_s), 1, tmp, work, stream))
+            GG_Z(zoom_base_window(z->plans[0], w[0], gg_cutoff_n2(z->box[0], r_s), tmp, chain, s2))
         } else {
-            for (int j = 0; j < 3; ++j)
-                GG_Z(gg_lowpass(z->plans[l - 1], static_cast<char*>(psi[l - 1]) + j * rp, gg_cutoff_n2(z->box[l - 1], r_s),
-                                1, static_cast<char*>(tmp) + j * rp, work, stream))
+            GG_Z(zoom_lowpass3(z->plans[l - 1], psi[l - 1], gg_cutoff_n2(z->box[l - 1], r_s), tmp, chain, s2))
         }
-        GG_Z(gg_interpolate_add_at(np, 2, d.origin[l], n, z->dtype, tmp, psi[l], stream))
-        GG_Z(gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], stream))
+        GG_ZH(hipStreamWaitEvent(s2, z->ev[kEvEq4 + l], 0))
+        GG_Z(gg_interpolate_add_at(np, 2, d.origin[l], n, z->dtype, tmp, psi[l], s2))
+        GG_ZH(hipEventRecord(z->ev[kEvPsi + l], s2))
     }
+    // the caller's stream: the base particles, then each level's particles
+    // as soon as its displacements are final (in parallel with the next
+    // level's Eq. 5, which only reads them)
+    GG_Z(gg_make_ic_from_noise(z->plans[0], w[0], 1.0, pos[0], vel[0], psi[0], wk + z->level_off[0], s0))
+    for (int l = 1; l < d.levels; ++l) {
+        GG_ZH(hipStreamWaitEvent(s0, z->ev[kEvPsi + l], 0))
+        GG_Z(gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], s0))
+    }
+    GG_ZH(hipEventRecord(z->ev[kEvEnd], s1))
+    GG_ZH(hipEventRecord(z->ev[kEvEnd + 1], s2))
+    GG_ZH(hipStreamWaitEvent(s0, z->ev[kEvEnd], 0))
+    GG_ZH(hipStreamWaitEvent(s0, z->ev[kEvEnd + 1], 0))
 #undef GG_Z
+#undef GG_ZH
     return GG_OK;
 }
 

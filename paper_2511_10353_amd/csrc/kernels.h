@@ -212,6 +212,11 @@ struct ZSrc {
     uint64_t ostride_comp;
     const T* psi;
     double* part;
+    // ZSRC_REAL with several fields: field blockIdx.y at w + blockIdx.y
+    // wstride_comp.  kout > 0 (plain rows, no Nyquist column): only modes
+    // k2 < kout are written, kout per line (a pruned half spectrum)
+    uint64_t wstride_comp;
+    int kout;
 };
 
 template <typename T, int N, int SRC, bool NYQ, bool BLK, int L = Tile<T>::L>
@@ -251,8 +256,9 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
             const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * p;
             cx<T> x0, x1;
             if constexpr (SRC == ZSRC_REAL) {
-                x0 = *reinterpret_cast<const cx<T>*>(zs.w + cell);
-                x1 = *reinterpret_cast<const cx<T>*>(zs.w + cell + 2);
+                const T* wsrc = zs.w + (uint64_t)blockIdx.y * zs.wstride_comp;
+                x0 = *reinterpret_cast<const cx<T>*>(wsrc + cell);
+                x1 = *reinterpret_cast<const cx<T>*>(wsrc + cell + 2);
             } else {
                 T a[4] = {(T)0, (T)0, (T)0, (T)0};
                 float4 b = {0.f, 0.f, 0.f, 0.f}, d = {0.f, 0.f, 0.f, 0.f};
@@ -280,8 +286,8 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
             lds[lidx<L>(p, cc)] = x0;
             lds[lidx<L>(p + 1, cc)] = x1;
         }
+        out += (uint64_t)blockIdx.y * zs.ostride_comp;
         if constexpr (SRC == ZSRC_GRAD) {
-            out += (uint64_t)blockIdx.y * zs.ostride_comp;
             if (zs.part) block_sum<NT>(dacc, zs.part + (uint64_t)blockIdx.y * gridDim.x + blockIdx.x);
         }
     }
@@ -307,6 +313,13 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
         const cx<T> o = {d.y * (T)0.5, -d.x * (T)0.5};
         return cadd(e, cmul(o, tw[k]));
     };
+    if constexpr (!NYQ && !BLK && SRC == ZSRC_REAL) {
+        if (zs.kout > 0) {
+            cx<T>* dk = out + line0 * zs.kout;
+            for (int fi = t; fi < L * zs.kout; fi += NT) dk[fi] = post(fi / zs.kout, fi % zs.kout);
+            return;
+        }
+    }
     cx<T>* dst = out + line0 * MO;
     if constexpr (NYQ) {
         for (int fi = t; fi < L * MO; fi += NT) dst[fi] = post(fi / MO, fi % MO);
@@ -368,7 +381,8 @@ __device__ __forceinline__ cx<T> c2r_pack(const cx<T>* lds, const cx<T>* tw, T n
 
 template <typename T, int N, bool BLK, int L = Tile<T>::L>
 __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(const cx<T>* __restrict__ in, int istride,
-                                                                   T* __restrict__ out, T scale, PlanView<T> pv) {
+                                                                   int kin, uint64_t icomp, T* __restrict__ out,
+                                                                   T scale, PlanView<T> pv, int kmul_field = -1) {
     constexpr int M = N / 2;
     constexpr int TPL = PlanInfo<M>::TPL;
     constexpr int NT = L * TPL;
@@ -378,8 +392,9 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(const cx<T>* 
     const int t = threadIdx.x;
     const int c = t % L, j = t / L;
     const uint64_t line0 = (uint64_t)blockIdx.x * L;
-    const cx<T>* src = in + line0 * istride;
-    if (istride == M) {
+    const cx<T>* src = in + (uint64_t)blockIdx.y * icomp + line0 * istride;
+    out += (uint64_t)blockIdx.y * N * N * N;
+    if (istride == M && kin == M) {
         for (int fi = t; fi < L * M / 2; fi += NT) {
             const int cc = fi / (M / 2), k = 2 * (fi % (M / 2));
             lds[lidx<L>(k, cc)] = src[2 * fi];
@@ -387,11 +402,17 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(const cx<T>* 
         }
         if (t < L) nyq[t] = (T)0;
     } else {
+        // rows of istride modes of which the first kin are stored (kin = M + 1:
+        // the full half spectrum; kin <= M: a pruned one, the rest zero)
+        // field kmul_field (a displacement's third component) is multiplied by
+        // its mode index k2, as the particle pass does
+        const bool kmul = (int)blockIdx.y == kmul_field;
         for (int fi = t; fi < L * M; fi += NT) {
             const int cc = fi / M, k = fi % M;
-            lds[lidx<L>(k, cc)] = src[(int64_t)cc * istride + k];
+            const cx<T> x = k < kin ? src[(int64_t)cc * istride + k] : cx<T>{(T)0, (T)0};
+            lds[lidx<L>(k, cc)] = kmul ? cscale(x, (T)k) : x;
         }
-        if (t < L) nyq[t] = src[(int64_t)t * istride + M].x;
+        if (t < L) nyq[t] = kin > M ? src[(int64_t)t * istride + M].x : (T)0;
     }
     __syncthreads();
     cx<T> v[V];
@@ -549,7 +570,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* _
 // same input is needed, the tile is read again (the re-read is served by the
 // caches) rather than held, which keeps the kernels free of register spills.
 // ---------------------------------------------------------------------------
-enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3, SMODE_XADJ = 4, SMODE_XDELTA = 5 };
+enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3, SMODE_XADJ = 4, SMODE_XDELTA = 5, SMODE_XWIN = 6 };
 
 template <typename T>
 struct StridedArgs {
@@ -568,6 +589,7 @@ struct StridedArgs {
     int cb0;  // first column block of this launch
     int o0;   // first outer index of this launch
     int xgroup;  // tile order across XCDs (see xcd_tile)
+    int64_t cstride;  // distance between the fields of blockIdx.y (0: one field)
 };
 
 // Tile of work-group b in a grid of nb work-groups.  The dispatcher hands
@@ -605,7 +627,8 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
     // wave-uniform tile base; lanes past the last column of a ragged tile
     // re-read the last valid column (so every per-lane offset is >= 0) and
     // store nothing
-    const int64_t tile = (int64_t)(o >> a.oshift) * a.ohi + (int64_t)(o & ((1 << a.oshift) - 1)) * a.olo + col0;
+    const int64_t tile = (int64_t)(o >> a.oshift) * a.ohi + (int64_t)(o & ((1 << a.oshift) - 1)) * a.olo + col0 +
+                         (int64_t)blockIdx.y * a.cstride;
     const int cl = valid ? c : a.ncols - 1 - col0;
     auto poff = [&](int p) -> int64_t {
         if constexpr (PBLK) return (int64_t)(p >> 3) * a.phi + (int64_t)(p & 7) * a.plo;
@@ -731,6 +754,36 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb) = v[i];
             }
+        }
+    } else if constexpr (MODE == SMODE_XWIN) {
+        // axis-0 forward, the Eq. 5 window n2_lo <= n^2 < n2_hi (with the
+        // cloud-in-cell deconvolution if set), axis-0 inverse; in0 -> out0
+        const uint32_t lb = lane_bytes(j);
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
+        __syncthreads();
+        fft_lines<T, N, L, -1, 1, RX>(v, lds, pv.tw, c, j);
+        const int s1 = signed_mode(o, N);
+        const int s2 = col;
+        const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
+        const T dline = pv.deconv ? cic_deconv<T>(s1, N) * cic_deconv<T>(s2, N) : (T)1;
+        const int jj = opaque(j);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const int k0 = last_pos<N, -1>(jj, i);
+            const int s0 = signed_mode(k0, N);
+            const int n2 = s0 * s0 + s1 * s1 + s2 * s2;
+            const bool zero = line_zero || (k0 == N / 2) || n2 < pv.n2_lo || n2 >= pv.n2_hi;
+            T f = zero ? (T)0 : (T)1;
+            if (pv.deconv) f *= cic_deconv<T>(s0, N) * dline;
+            v[i] = cscale(v[i], f);
+        }
+        const int cc = opaque(c);
+        fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);
+        const uint32_t lb2 = lane_bytes(jj);
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb2) = v[i];
         }
     } else if constexpr (MODE == SMODE_XDELTA) {
         const TauLookup<T> taul = tau_lookup(pv);

@@ -79,6 +79,18 @@ struct Ops {
                               hipStream_t s);
     // Eq. 5 on a real field: modes with n^2 >= n2_max dropped, optional CiC
     // deconvolution; out (R) may equal field; work: two plain half spectra
+    // Eq. 5 as the filter of a noise field restricted to n^2 < n2_max (with
+    // the cloud-in-cell deconvolution if set): psi (3 R).  The half spectrum
+    // is pruned to the window's columns (work: 3 N N kc complex values); a
+    // window too wide for that runs the fused path with the window.
+    static hipError_t windowed_displacements(const PlanView<T>& pv, const T* w, int n2_max, int deconv, T* psi,
+                                             cx<T>* work, const ExecCtx& x);
+    // Eq. 5 on three fields at once (field, out: 3 consecutive R arrays, out
+    // distinct from field): modes beyond the window are never transformed
+    // along axes 1 and 0 (the half spectrum is pruned to the window's
+    // columns).  work: 3 N N kc complex values at most (kc <= N / 2).
+    static hipError_t lowpass3(const PlanView<T>& pv, const T* field, int n2_max, int deconv, T* out, cx<T>* work,
+                               hipStream_t s);
     static hipError_t lowpass(const PlanView<T>& pv, const T* field, int n2_max, int deconv, T* out, cx<T>* work,
                               hipStream_t s);
     // Sec. 2.3 degrade: NGP values of the (factor n)^3 fine field on the plan's

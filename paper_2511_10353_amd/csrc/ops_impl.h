@@ -77,14 +77,14 @@ template <typename T>
 StridedArgs<T> strided_args(const cx<T>* in0, const cx<T>* in1, cx<T>* out0, cx<T>* out1, cx<T>* out2, int64_t ohi,
                             int64_t olo, int oshift, int64_t pstride, int64_t phi, int64_t plo, int ncols,
                             const cx<T>* in2 = nullptr) {
-    return StridedArgs<T>{in0, in1, in2, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0, 2};
+    return StridedArgs<T>{in0, in1, in2, out0, out1, out2, ohi, olo, oshift, pstride, phi, plo, ncols, 0, 0, 0, 2, 0};
 }
 
 // Launches tiles o in [o0, o0 + no) x column blocks [cb0, cb0 + nb) (nb = 0:
 // all column blocks; no = 0: all N outer indices).
 template <typename T, int N, int MODE, bool PBLK = false, int L = Tile<T>::L>
 hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStream_t s, int o0 = 0, int no = 0,
-                          int cb0 = 0, int nb = 0) {
+                          int cb0 = 0, int nb = 0, int nfields = 1) {
     StridedArgs<T> a = a0;
     const int ncb_all = (a.ncols + L - 1) / L;
     if (nb == 0) nb = ncb_all;
@@ -98,7 +98,8 @@ hipError_t launch_strided(const StridedArgs<T>& a0, const PlanView<T>& pv, hipSt
     const int jmax = PlanInfo<N>::TPL - 1;
     const int64_t prow = PBLK ? (int64_t)(jmax >> 3) * a.phi + (int64_t)(jmax & 7) * a.plo : (int64_t)jmax * a.pstride;
     if (a.ncols < 1 || (prow + L) * (int64_t)sizeof(cx<T>) >= (int64_t)1 << 32) return hipErrorInvalidValue;
-    const unsigned grid = (unsigned)(no * nb);
+    if (nfields < 1 || (nfields > 1 && a.cstride <= 0)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(no * nb), (unsigned)nfields);
     k_strided<T, N, MODE, L, PBLK><<<grid, L * PlanInfo<N>::TPL, 0, s>>>(a, pv);
     return hipGetLastError();
 }
@@ -163,7 +164,7 @@ hipError_t Ops<T>::fft_inverse(const PlanView<T>& pv, const cx<T>* in, T* out, c
             strided_args<T>(work, nullptr, work, nullptr, nullptr, N * R, 0, 0, R, 0, 0, M + 1), pv, s);
         if (e != hipSuccess) return e;
         const T scale = (T)(1.0 / ((double)N * (double)N * (double)N));
-        k_zinv<T, N, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(work, M + 1, out, scale, pv);
+        k_zinv<T, N, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(work, M + 1, M + 1, 0, out, scale, pv);
         return hipGetLastError();
     });
 }
@@ -374,7 +375,7 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
         GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
                                                 pv, s)))
         // A5: axis-2 c2r -> d loss / d W (the 1/N^3 is inside tau)
-        k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, gw, (T)1, pv);
+        k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, M, 0, gw, (T)1, pv);
         GG_TRY(hipGetLastError())
 #undef GG_TRY
         return hipSuccess;
@@ -406,7 +407,7 @@ hipError_t Ops<T>::density(const PlanView<T>& pv, uint64_t seed, const T* w, T* 
             strided_args<T>(b0, nullptr, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M), pv, s)))
         GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
                                                 pv, s)))
-        k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, delta, (T)1, pv);
+        k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, M, 0, delta, (T)1, pv);
         GG_TRY(hipGetLastError())
 #undef GG_TRY
         return hipSuccess;
@@ -490,6 +491,95 @@ hipError_t Ops<T>::cic_add(const T* src, int n_src, int num, int den, const int 
     k_cic_add<T><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc), 3), bc, 0, s>>>(
         src, n_src, num, den, origin[0], origin[1], origin[2], dst, n_dst);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Ops<T>::lowpass3(const PlanView<T>& pv0, const T* field, int n2_max, int deconv, T* out, cx<T>* work,
+                            hipStream_t s) {
+    const int n = pv0.n;
+    const uint64_t n3 = (uint64_t)n * n * n;
+    // modes |n_j| <= kmax survive the window n^2 < n2_max: the half spectrum
+    // is kept to kc columns (whole column blocks); without room for that, the
+    // full transform per field
+    int kmax = 0;
+    while ((int64_t)(kmax + 1) * (kmax + 1) < (int64_t)n2_max) ++kmax;
+    constexpr int L = Tile<T>::L;
+    const int kc = (kmax + 1 + L - 1) / L * L;
+    if (n2_max <= 0 || kc >= n / 2) {
+        for (int j = 0; j < 3; ++j) {
+            const hipError_t e = lowpass(pv0, field + j * n3, n2_max, deconv, out + j * n3, work, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    PlanView<T> pv = pv0;
+    pv.n2_lo = 0;
+    pv.n2_hi = n2_max;
+    pv.deconv = deconv ? 1 : 0;
+    return dispatch_n(n, [&](auto nc) -> hipError_t {
+        constexpr int N = decltype(nc)::value;
+        constexpr int M = N / 2;
+        const int64_t fs = (int64_t)N * N * kc;  // one pruned spectrum
+        ZSrc<T> zs{field, nullptr, nullptr, nullptr, 0.0, (uint64_t)fs, nullptr, nullptr};
+        zs.wstride_comp = n3;
+        zs.kout = kc;
+        k_zfwd<T, N, ZSRC_REAL, false, false><<<dim3(N * N / L, 3), L * PlanInfo<M>::TPL, 0, s>>>(zs, work, pv.tw, 0, 0,
+                                                                                                  0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // axis 1: o = m0 (rows m1, kc columns); axis 0: o = k1 (rows k0)
+        StridedArgs<T> a1 = strided_args<T>(work, nullptr, work, nullptr, nullptr, (int64_t)N * kc, 0, 0, kc, 0, 0, kc);
+        StridedArgs<T> a0 = strided_args<T>(work, nullptr, work, nullptr, nullptr, kc, 0, 0, (int64_t)N * kc, 0, 0, kc);
+        a1.cstride = a0.cstride = fs;
+        if ((e = launch_strided<T, N, SMODE_FWD>(a1, pv, s, 0, 0, 0, 0, 3)) != hipSuccess) return e;
+        if ((e = launch_strided<T, N, SMODE_XWIN>(a0, pv, s, 0, 0, 0, 0, 3)) != hipSuccess) return e;
+        if ((e = launch_strided<T, N, SMODE_INV>(a1, pv, s, 0, 0, 0, 0, 3)) != hipSuccess) return e;
+        const T scale = (T)(1.0 / ((double)N * (double)N * (double)N));
+        k_zinv<T, N, false><<<dim3(N * N / L, 3), L * PlanInfo<M>::TPL, 0, s>>>(work, kc, kc, (uint64_t)fs, out, scale,
+                                                                               pv);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+hipError_t Ops<T>::windowed_displacements(const PlanView<T>& pv0, const T* w, int n2_max, int deconv, T* psi,
+                                          cx<T>* work, const ExecCtx& x) {
+    const int n = pv0.n;
+    int kmax = 0;
+    while ((int64_t)(kmax + 1) * (kmax + 1) < (int64_t)n2_max) ++kmax;
+    constexpr int L = Tile<T>::L;
+    const int kc = (kmax + 1 + L - 1) / L * L;
+    PlanView<T> pv = pv0;
+    pv.n2_lo = 0;
+    pv.n2_hi = n2_max;
+    pv.deconv = deconv ? 1 : 0;
+    if (n2_max <= 0 || kc >= n / 2) return make_ic_from_noise(pv, w, nullptr, nullptr, psi, work, x);
+    const hipStream_t s = x.a;
+    return dispatch_n(n, [&](auto nc) -> hipError_t {
+        constexpr int N = decltype(nc)::value;
+        constexpr int M = N / 2;
+        const int64_t fs = (int64_t)N * N * kc;  // one pruned spectrum
+        cx<T>* s0 = work;
+        cx<T>* s1 = work + fs;
+        cx<T>* s2 = work + 2 * fs;
+        ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+        zs.kout = kc;
+        k_zfwd<T, N, ZSRC_REAL, false, false><<<N * N / L, L * PlanInfo<M>::TPL, 0, s>>>(zs, s0, pv.tw, 0, 0, 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // axis 1 forward; axis 0: F = IFFT(i s0 tau' W~), G = IFFT(i tau' W~) with
+        // tau' the filter on the window; axis 1: A = IFFT(F), B = IFFT(s1 G),
+        // C = IFFT(G); c2r of A, B and s2 C
+        const StridedArgs<T> a1 = strided_args<T>(s0, nullptr, s0, nullptr, nullptr, (int64_t)N * kc, 0, 0, kc, 0, 0, kc);
+        if ((e = launch_strided<T, N, SMODE_FWD>(a1, pv, s)) != hipSuccess) return e;
+        const StridedArgs<T> a3 = strided_args<T>(s0, nullptr, s1, s2, nullptr, kc, 0, 0, (int64_t)N * kc, 0, 0, kc);
+        if ((e = launch_strided<T, N, SMODE_XFILT>(a3, pv, s)) != hipSuccess) return e;
+        const StridedArgs<T> a4 = strided_args<T>(s1, s2, s0, s1, s2, (int64_t)N * kc, 0, 0, kc, 0, 0, kc);
+        if ((e = launch_strided<T, N, SMODE_YINV3>(a4, pv, s)) != hipSuccess) return e;
+        k_zinv<T, N, false><<<dim3(N * N / L, 3), L * PlanInfo<M>::TPL, 0, s>>>(s0, kc, kc, (uint64_t)fs, psi, (T)1, pv,
+                                                                               2);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>

@@ -57,6 +57,7 @@ int main(void) {
   printf("%zu %zu\n", offsetof(gg_plan_info, p1_lines), offsetof(gg_plan_info, z_lines));
   printf("%zu %zu %zu\n", sizeof(gg_tune_entry), offsetof(gg_tune_entry, ms), sizeof(gg_zoom_desc));
   printf("%zu %zu %zu\n", offsetof(gg_zoom_desc, origin), offsetof(gg_zoom_desc, box), offsetof(gg_zoom_desc, variant));
+  printf("%zu %zu\n", sizeof(gg_zoom_tune_entry), offsetof(gg_zoom_tune_entry, ms));
   return 0;
 }
 ''')
@@ -68,7 +69,8 @@ int main(void) {
             binding._Info.box.offset, binding._Info.real_elems.offset, binding._Info.workspace_bytes.offset,
             binding._Info.chunks.offset, binding._Info.p1_lines.offset, binding._Info.z_lines.offset,
             ctypes.sizeof(binding._TuneEntry), binding._TuneEntry.ms.offset, ctypes.sizeof(binding._ZoomDesc),
-            binding._ZoomDesc.origin.offset, binding._ZoomDesc.box.offset, binding._ZoomDesc.variant.offset]
+            binding._ZoomDesc.origin.offset, binding._ZoomDesc.box.offset, binding._ZoomDesc.variant.offset,
+            ctypes.sizeof(binding._ZoomTuneEntry), binding._ZoomTuneEntry.ms.offset]
     assert got == want
 
 

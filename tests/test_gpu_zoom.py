@@ -174,3 +174,27 @@ def test_zoom_rejects_bad_descriptions():
         gg.Zoom(64, 100.0, [100], [(0, 0, 0)])  # unsupported size
     with pytest.raises(gg.GGError):
         gg.Zoom(64, 100.0, [96, 64], [(0, 0, 0), (80, 0, 0)])  # level 2 outside its parent
+
+
+def test_zoom_autotune_keeps_the_bits():
+    # every tile width gives the same bits, so the tuned hierarchy (eager and
+    # replayed graph) reproduces the untuned run exactly
+    n0, box0 = 64, 100.0
+    sizes, origins = [96, 64], [(50, 3, 17), (30, 36, 26)]
+    z = gg.Zoom(n0, box0, sizes, origins, dtype="f32")
+    z.run(9)
+    torch.cuda.synchronize()
+    before = [{k: v.clone() for k, v in lv.items()} for lv in z.levels]
+    table = z.autotune(seed=9, reps=1)
+    say(f"[zoom autotune] {table}")
+    assert {e["level"] for e in table} == {0, 1, 2}
+    assert all(e["ms"] > 0 for e in table)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for use_graph in (False, True):
+            z.run(9, use_graph=use_graph)
+            torch.cuda.synchronize()
+            for lv, ev in zip(z.levels, before):
+                for k in ev:
+                    assert torch.equal(lv[k], ev[k]), (use_graph, k)
+    z.close()
