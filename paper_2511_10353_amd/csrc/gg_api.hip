@@ -1085,9 +1085,9 @@ gg_status gg_timing_read(gg_plan* p, double* ms, int npass, int* ncalls) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Zoom hierarchy (Sec. 2.3-2.4): one plan per level, run as one sequence of
-// launches on one stream, optionally captured once into a HIP graph and
-// replayed.
+// Zoom hierarchy (Sec. 2.3-2.4): one plan per level, run on the caller's
+// stream and two streams of the hierarchy ordered by events, optionally
+// captured once into a HIP graph and replayed.
 // ---------------------------------------------------------------------------
 struct gg_zoom {
     gg_zoom_desc d{};
@@ -1359,42 +1359,64 @@ gg_status zoom_sequence(gg_zoom* z, uint64_t seed, void* const* w, void* const* 
     GG_ZH(hipEventRecord(z->ev[kEvW0], s0))
     GG_ZH(hipStreamWaitEvent(s1, z->ev[kEvW0], 0))
     GG_ZH(hipStreamWaitEvent(s2, z->ev[kEvW0], 0))
-    // side[0]: each level's noise (App. A refinement of its parent's sub-box)
-    // and its small scales (Eq. 4 on the level's own periodic sub-box)
-    for (int l = 1; l < d.levels; ++l) {
+    // the caller's stream: the base particles
+    auto base = [&]() -> gg_status {
+        return gg_make_ic_from_noise(z->plans[0], w[0], 1.0, pos[0], vel[0], psi[0], wk + z->level_off[0], s0);
+    };
+    // side[0]: the level's noise (App. A refinement of its parent's sub-box)
+    // and its small scales (Eq. 4 on its own periodic sub-box)
+    auto small = [&](int l) -> gg_status {
         const int np = d.n[l - 1], n = d.n[l];
         const double r_s = 2.0 * z->cell[l - 1];
-        GG_Z(gg_refine_noise_region(np, d.origin[l], n / 2, z->dtype, (gg_refine)d.variant, w[l - 1], seed, (uint32_t)l,
-                                    w[l], s1))
-        GG_Z(gg_make_displacements(z->plans[l], w[l], gg_cutoff_n2(z->box[l], r_s), 0, 0, psi[l], wk + z->level_off[l],
-                                   s1))
-        GG_ZH(hipEventRecord(z->ev[kEvEq4 + l], s1))
-    }
-    // side[1]: the large scales of each level (Eq. 5 of its parent's final
-    // displacements, CiC-interpolated), which chain from level to level
-    for (int l = 1; l < d.levels; ++l) {
-        const int np = d.n[l - 1], n = d.n[l];
+        gg_status r = gg_refine_noise_region(np, d.origin[l], n / 2, z->dtype, (gg_refine)d.variant, w[l - 1], seed,
+                                             (uint32_t)l, w[l], s1);
+        if (r != GG_OK) return r;
+        r = gg_make_displacements(z->plans[l], w[l], gg_cutoff_n2(z->box[l], r_s), 0, 0, psi[l], wk + z->level_off[l],
+                                  s1);
+        if (r != GG_OK) return r;
+        const hipError_t he = hipEventRecord(z->ev[kEvEq4 + l], s1);
+        return he == hipSuccess ? GG_OK : fail_hip(he, "zoom stream ordering");
+    };
+    // side[1]: the level's large scales (Eq. 5 of its parent's final
+    // displacements), chained from level to level ...
+    auto large = [&](int l) -> gg_status {
         const double r_s = 2.0 * z->cell[l - 1];
         if (l == 1) {
             // the base displacements are the filtered base noise, so Eq. 5 of them
             // is that filter on the large-scale window: one fused pass sequence
             // over the base noise instead of three transform round trips
-            GG_Z(zoom_base_window(z->plans[0], w[0], gg_cutoff_n2(z->box[0], r_s), tmp, chain, s2))
-        } else {
-            GG_Z(zoom_lowpass3(z->plans[l - 1], psi[l - 1], gg_cutoff_n2(z->box[l - 1], r_s), tmp, chain, s2))
+            return zoom_base_window(z->plans[0], w[0], gg_cutoff_n2(z->box[0], r_s), tmp, chain, s2);
         }
-        GG_ZH(hipStreamWaitEvent(s2, z->ev[kEvEq4 + l], 0))
-        GG_Z(gg_interpolate_add_at(np, 2, d.origin[l], n, z->dtype, tmp, psi[l], s2))
-        GG_ZH(hipEventRecord(z->ev[kEvPsi + l], s2))
-    }
-    // the caller's stream: the base particles, then each level's particles
-    // as soon as its displacements are final (in parallel with the next
-    // level's Eq. 5, which only reads them)
-    GG_Z(gg_make_ic_from_noise(z->plans[0], w[0], 1.0, pos[0], vel[0], psi[0], wk + z->level_off[0], s0))
+        return zoom_lowpass3(z->plans[l - 1], psi[l - 1], gg_cutoff_n2(z->box[l - 1], r_s), tmp, chain, s2);
+    };
+    // ... CiC-interpolated onto the level once its small scales exist
+    auto join = [&](int l) -> gg_status {
+        hipError_t he = hipStreamWaitEvent(s2, z->ev[kEvEq4 + l], 0);
+        if (he != hipSuccess) return fail_hip(he, "zoom stream ordering");
+        const gg_status r = gg_interpolate_add_at(d.n[l - 1], 2, d.origin[l], d.n[l], z->dtype, tmp, psi[l], s2);
+        if (r != GG_OK) return r;
+        he = hipEventRecord(z->ev[kEvPsi + l], s2);
+        return he == hipSuccess ? GG_OK : fail_hip(he, "zoom stream ordering");
+    };
+    // the caller's stream: a level's particles once its displacements are final
+    auto particles = [&](int l) -> gg_status {
+        const hipError_t he = hipStreamWaitEvent(s0, z->ev[kEvPsi + l], 0);
+        if (he != hipSuccess) return fail_hip(he, "zoom stream ordering");
+        return gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], s0);
+    };
+    // Issue order: every level's small scales, then the chain of large
+    // scales, then the base and level particles.  A captured graph keeps this
+    // order in how it spreads the branches over hardware queues: issuing the
+    // base particles or a level's large scales first measured slower replayed
+    // (1.25-1.59 ms per hierarchy against 1.20 ms), and no order changed the
+    // eager time (1.22 ms).
+    for (int l = 1; l < d.levels; ++l) GG_Z(small(l))
     for (int l = 1; l < d.levels; ++l) {
-        GG_ZH(hipStreamWaitEvent(s0, z->ev[kEvPsi + l], 0))
-        GG_Z(gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], s0))
+        GG_Z(large(l))
+        GG_Z(join(l))
     }
+    GG_Z(base())
+    for (int l = 1; l < d.levels; ++l) GG_Z(particles(l))
     GG_ZH(hipEventRecord(z->ev[kEvEnd], s1))
     GG_ZH(hipEventRecord(z->ev[kEvEnd + 1], s2))
     GG_ZH(hipStreamWaitEvent(s0, z->ev[kEvEnd], 0))

@@ -488,7 +488,7 @@ hipError_t Ops<T>::cic_add(const T* src, int n_src, int num, int den, const int 
         if (origin[a] < 0 || origin[a] >= n_src) return hipErrorInvalidValue;
     if (n_dst > 4096) return hipErrorInvalidValue;
     const unsigned bc = n_dst < 256 ? (unsigned)((n_dst + 63) / 64 * 64) : 256u;
-    k_cic_add<T><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc), 3), bc, 0, s>>>(
+    k_cic_add<T><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc)), bc, 0, s>>>(
         src, n_src, num, den, origin[0], origin[1], origin[2], dst, n_dst);
     return hipGetLastError();
 }

@@ -210,35 +210,56 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
 // axis (num / den = 1 / R for a refinement by an integer R, n_src / n_dst in
 // lowest terms for a whole box resampled to another size).  Cell and weight
 // come from exact integer arithmetic; products and sums in binary64, then
-// rounded to T.
+// rounded to T.  A work-group covers one destination row (x, y) and a run of
+// z: the row's cells and weights along axes 0 and 1 are the same for every
+// thread, and each thread does all three fields, so the integer arithmetic
+// is done once per point and 24 independent loads are in flight per thread.
 template <typename T>
 __global__ void k_cic_add(const T* __restrict__ src, int ns, int num, int den, int o0, int o1, int o2,
                           T* __restrict__ dst, int nd) {
-    // block: one destination row (x, y) = blockIdx.x and a run of z; comp = blockIdx.z
     const int z = blockIdx.y * blockDim.x + threadIdx.x;
     if (z >= nd) return;
     const int row = blockIdx.x;
     const int x = row / nd, y = row - x * nd;
     const uint64_t n3d = (uint64_t)nd * nd * nd;
     const uint64_t n3s = (uint64_t)ns * ns * ns;
-    const int comp = blockIdx.z;
     // point m sits at o + m num / den source cells: cell o + floor(m num / den), weight (m num mod den) / den
     const int xn = x * num, yn = y * num, zn = z * num;
     const int x0 = (o0 + xn / den) % ns, y0 = (o1 + yn / den) % ns, z0 = (o2 + zn / den) % ns;
     const double tx = (double)(xn % den) / den, ty = (double)(yn % den) / den, tz = (double)(zn % den) / den;
     const int x1 = x0 + 1 == ns ? 0 : x0 + 1, y1 = y0 + 1 == ns ? 0 : y0 + 1, z1 = z0 + 1 == ns ? 0 : z0 + 1;
-    const T* s = src + comp * n3s;
-    auto at = [&](int i, int j, int k) { return (double)s[((uint64_t)i * ns + j) * ns + k]; };
-    // interpolate along axis 0, then 1, then 2 (the oracle's order)
-    const double a00 = at(x0, y0, z0) * (1.0 - tx) + at(x1, y0, z0) * tx;
-    const double a10 = at(x0, y1, z0) * (1.0 - tx) + at(x1, y1, z0) * tx;
-    const double a01 = at(x0, y0, z1) * (1.0 - tx) + at(x1, y0, z1) * tx;
-    const double a11 = at(x0, y1, z1) * (1.0 - tx) + at(x1, y1, z1) * tx;
-    const double b0 = a00 * (1.0 - ty) + a10 * ty;
-    const double b1 = a01 * (1.0 - ty) + a11 * ty;
-    const double v = b0 * (1.0 - tz) + b1 * tz;
-    T* d = dst + comp * n3d + (uint64_t)row * nd + z;
-    *d = (T)((double)*d + v);
+    // offsets of the four (axis 0, axis 1) corners' rows
+    const uint64_t r00 = ((uint64_t)x0 * ns + y0) * ns, r10 = ((uint64_t)x1 * ns + y0) * ns;
+    const uint64_t r01 = ((uint64_t)x0 * ns + y1) * ns, r11 = ((uint64_t)x1 * ns + y1) * ns;
+    T c[3][8];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const T* s = src + comp * n3s;
+        c[comp][0] = s[r00 + z0];
+        c[comp][1] = s[r10 + z0];
+        c[comp][2] = s[r01 + z0];
+        c[comp][3] = s[r11 + z0];
+        c[comp][4] = s[r00 + z1];
+        c[comp][5] = s[r10 + z1];
+        c[comp][6] = s[r01 + z1];
+        c[comp][7] = s[r11 + z1];
+    }
+    T* d = dst + (uint64_t)row * nd + z;
+    T old[3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) old[comp] = d[comp * n3d];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        // interpolate along axis 0, then 1, then 2 (the oracle's order)
+        const double a00 = (double)c[comp][0] * (1.0 - tx) + (double)c[comp][1] * tx;
+        const double a10 = (double)c[comp][2] * (1.0 - tx) + (double)c[comp][3] * tx;
+        const double a01 = (double)c[comp][4] * (1.0 - tx) + (double)c[comp][5] * tx;
+        const double a11 = (double)c[comp][6] * (1.0 - tx) + (double)c[comp][7] * tx;
+        const double b0 = a00 * (1.0 - ty) + a10 * ty;
+        const double b1 = a01 * (1.0 - ty) + a11 * ty;
+        const double v = b0 * (1.0 - tz) + b1 * tz;
+        d[comp * n3d] = (T)((double)old[comp] + v);
+    }
 }
 
 }  // namespace gg

@@ -46,6 +46,21 @@ def test_refine_noise_against_oracle(variant, n, dtype):
         assert ulp <= 1
 
 
+@pytest.mark.parametrize("variant,n", [("hr", 64), ("3", 48), ("4", 128), ("linear", 32), ("sine", 32)])
+def test_refine_float_is_rounded_double(variant, n):
+    # the float kernel forms its Gaussians by the fast evaluation and redoes a
+    # work-group exactly when a child could round differently: its children
+    # must equal the double kernel's children rounded once, bit for bit
+    parent = torch.from_numpy(onoise.noise_grid(n, 4).astype(np.float32)).cuda()
+    f32 = gg.refine_noise(parent, variant, seed=33, stream_id=2)
+    f64 = gg.refine_noise(parent.double(), variant, seed=33, stream_id=2)
+    torch.cuda.synchronize()
+    want = f64.float()
+    bad = int((f32.view(torch.int32) != want.view(torch.int32)).sum())
+    say(f"[refine] {variant} n={n} float vs rounded double: {bad} of {f32.numel()} differ")
+    assert bad == 0
+
+
 def test_refine_rejects_bad_arguments():
     w = torch.zeros((9, 9, 9), device="cuda")
     with pytest.raises(gg.GGError):
