@@ -1097,10 +1097,11 @@ struct gg_zoom {
     std::vector<std::array<double, 3>> origin_box;  // level origin in the base box
     size_t plan_work = 0;                           // max plan workspace
     size_t tmp_bytes = 0;                           // 3 R of the largest parent
-    // the hierarchy runs as three streams: the caller's (base particles, the
-    // levels' particles), side[0] (noise refinement and Eq. 4 of every level,
-    // which depend on the noise only) and side[1] (the chain of Eq. 5 and the
-    // CiC interpolation, level by level); events order them
+    // the hierarchy runs as three streams: the caller's (base noise and base
+    // particles), side[0] (noise refinement and Eq. 4 of every level, which
+    // depend on the noise only) and side[1] (the chain of Eq. 5 and the CiC
+    // interpolation with the level's particles, level by level); events order
+    // them
     hipStream_t side[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ev;  // kZoomEvents
     // workspace layout (bytes from the start): the chain's transform work and
@@ -1118,13 +1119,12 @@ struct gg_zoom {
 
 namespace {
 
-// events per hierarchy: base noise done, Eq. 4 of level l done (8), psi of
-// level l final (8), the two side streams done (2)
-constexpr int kZoomEvents = 1 + 2 * GG_ZOOM_MAX_LEVELS + 2;
+// events per hierarchy: base noise done, Eq. 4 of level l done (8), the two
+// side streams done (2)
+constexpr int kZoomEvents = 1 + GG_ZOOM_MAX_LEVELS + 2;
 constexpr int kEvW0 = 0;
 constexpr int kEvEq4 = 1;
-constexpr int kEvPsi = 1 + GG_ZOOM_MAX_LEVELS;
-constexpr int kEvEnd = 1 + 2 * GG_ZOOM_MAX_LEVELS;
+constexpr int kEvEnd = 1 + GG_ZOOM_MAX_LEVELS;
 
 void zoom_free(gg_zoom* z) {
     if (!z) return;
@@ -1389,34 +1389,40 @@ gg_status zoom_sequence(gg_zoom* z, uint64_t seed, void* const* w, void* const* 
         }
         return zoom_lowpass3(z->plans[l - 1], psi[l - 1], gg_cutoff_n2(z->box[l - 1], r_s), tmp, chain, s2);
     };
-    // ... CiC-interpolated onto the level once its small scales exist
+    // ... CiC-interpolated onto the level once its small scales exist; the
+    // same pass writes the level's particles (Eq. 3 at the level's lattice in
+    // the base box) from the final displacements
     auto join = [&](int l) -> gg_status {
         hipError_t he = hipStreamWaitEvent(s2, z->ev[kEvEq4 + l], 0);
         if (he != hipSuccess) return fail_hip(he, "zoom stream ordering");
-        const gg_status r = gg_interpolate_add_at(d.n[l - 1], 2, d.origin[l], d.n[l], z->dtype, tmp, psi[l], s2);
-        if (r != GG_OK) return r;
-        he = hipEventRecord(z->ev[kEvPsi + l], s2);
-        return he == hipSuccess ? GG_OK : fail_hip(he, "zoom stream ordering");
+        const gg_plan* pl = z->plans[l];
+        const int o[3] = {d.origin[l][0], d.origin[l][1], d.origin[l][2]};
+        if (pl->dtype == GG_F64) {
+            auto v = view<double>(pl);
+            for (int a = 0; a < 3; ++a) v.origin[a] = z->origin_box[l][a];
+            v.wrap = d.box;
+            he = gg::Ops<double>::cic_add_zel(static_cast<const double*>(tmp), d.n[l - 1], 1, 2, o,
+                                              static_cast<double*>(psi[l]), v, pos[l], vel[l], s2);
+        } else {
+            auto v = view<float>(pl);
+            for (int a = 0; a < 3; ++a) v.origin[a] = z->origin_box[l][a];
+            v.wrap = d.box;
+            he = gg::Ops<float>::cic_add_zel(static_cast<const float*>(tmp), d.n[l - 1], 1, 2, o,
+                                             static_cast<float*>(psi[l]), v, pos[l], vel[l], s2);
+        }
+        return he == hipSuccess ? GG_OK : fail_hip(he, "zoom interpolation launch");
     };
-    // the caller's stream: a level's particles once its displacements are final
-    auto particles = [&](int l) -> gg_status {
-        const hipError_t he = hipStreamWaitEvent(s0, z->ev[kEvPsi + l], 0);
-        if (he != hipSuccess) return fail_hip(he, "zoom stream ordering");
-        return gg_zeldovich_at(z->plans[l], psi[l], z->origin_box[l].data(), d.box, pos[l], vel[l], s0);
-    };
-    // Issue order: every level's small scales, then the chain of large
-    // scales, then the base and level particles.  A captured graph keeps this
-    // order in how it spreads the branches over hardware queues: issuing the
-    // base particles or a level's large scales first measured slower replayed
-    // (1.25-1.59 ms per hierarchy against 1.20 ms), and no order changed the
-    // eager time (1.22 ms).
+    // Issue order: every level's small scales, then the chain of large scales
+    // (with the level particles), then the base particles.  A captured graph
+    // keeps this order in how it spreads the branches over hardware queues:
+    // issuing the base particles or a level's large scales first measured
+    // slower replayed, and no order changed the eager time.
     for (int l = 1; l < d.levels; ++l) GG_Z(small(l))
     for (int l = 1; l < d.levels; ++l) {
         GG_Z(large(l))
         GG_Z(join(l))
     }
     GG_Z(base())
-    for (int l = 1; l < d.levels; ++l) GG_Z(particles(l))
     GG_ZH(hipEventRecord(z->ev[kEvEnd], s1))
     GG_ZH(hipEventRecord(z->ev[kEvEnd + 1], s2))
     GG_ZH(hipStreamWaitEvent(s0, z->ev[kEvEnd], 0))

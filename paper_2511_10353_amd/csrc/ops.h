@@ -77,6 +77,10 @@ struct Ops {
     // src (3 fields of n_src^3) at origin + m num / den (src cells)
     static hipError_t cic_add(const T* src, int n_src, int num, int den, const int origin[3], T* dst, int n_dst,
                               hipStream_t s);
+    // cic_add onto the lattice of pv (n_dst = pv.n) and Eq. (3) of the result
+    // at pv's lattice (origin, wrap) in the same pass
+    static hipError_t cic_add_zel(const T* src, int n_src, int num, int den, const int origin[3], T* dst,
+                                  const PlanView<T>& pv, float* pos, float* vel, hipStream_t s);
     // Eq. 5 on a real field: modes with n^2 >= n2_max dropped, optional CiC
     // deconvolution; out (R) may equal field; work: two plain half spectra
     // Eq. 5 as the filter of a noise field restricted to n^2 < n2_max (with

@@ -488,8 +488,22 @@ hipError_t Ops<T>::cic_add(const T* src, int n_src, int num, int den, const int 
         if (origin[a] < 0 || origin[a] >= n_src) return hipErrorInvalidValue;
     if (n_dst > 4096) return hipErrorInvalidValue;
     const unsigned bc = n_dst < 256 ? (unsigned)((n_dst + 63) / 64 * 64) : 256u;
-    k_cic_add<T><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc)), bc, 0, s>>>(
-        src, n_src, num, den, origin[0], origin[1], origin[2], dst, n_dst);
+    k_cic_add<T, false><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc)), bc, 0, s>>>(
+        src, n_src, num, den, origin[0], origin[1], origin[2], dst, n_dst, PlanView<T>{}, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Ops<T>::cic_add_zel(const T* src, int n_src, int num, int den, const int origin[3], T* dst,
+                               const PlanView<T>& pv, float* pos, float* vel, hipStream_t s) {
+    const int n_dst = pv.n;
+    if (n_src < 1 || n_dst < 1 || num < 1 || den < 1) return hipErrorInvalidValue;
+    for (int a = 0; a < 3; ++a)
+        if (origin[a] < 0 || origin[a] >= n_src) return hipErrorInvalidValue;
+    if (n_dst > 4096) return hipErrorInvalidValue;
+    const unsigned bc = n_dst < 256 ? (unsigned)((n_dst + 63) / 64 * 64) : 256u;
+    k_cic_add<T, true><<<dim3((unsigned)(n_dst * n_dst), (unsigned)((n_dst + bc - 1) / bc)), bc, 0, s>>>(
+        src, n_src, num, den, origin[0], origin[1], origin[2], dst, n_dst, pv, pos, vel);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.h"
 #include "noise_dev.h"
 
 namespace gg {
@@ -214,9 +215,13 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine(const T* __restrict__
 // z: the row's cells and weights along axes 0 and 1 are the same for every
 // thread, and each thread does all three fields, so the integer arithmetic
 // is done once per point and 24 independent loads are in flight per thread.
-template <typename T>
+// ZEL: the point's final displacement also gives its particle (Eq. 3 on the
+// lattice of pv, as k_zeldovich): a zoom level's particles without reading
+// the field back.
+template <typename T, bool ZEL>
 __global__ void k_cic_add(const T* __restrict__ src, int ns, int num, int den, int o0, int o1, int o2,
-                          T* __restrict__ dst, int nd) {
+                          T* __restrict__ dst, int nd, PlanView<T> pv, float* __restrict__ pos,
+                          float* __restrict__ vel) {
     const int z = blockIdx.y * blockDim.x + threadIdx.x;
     if (z >= nd) return;
     const int row = blockIdx.x;
@@ -258,7 +263,13 @@ __global__ void k_cic_add(const T* __restrict__ src, int ns, int num, int den, i
         const double b0 = a00 * (1.0 - ty) + a10 * ty;
         const double b1 = a01 * (1.0 - ty) + a11 * ty;
         const double v = b0 * (1.0 - tz) + b1 * tz;
-        d[comp * n3d] = (T)((double)old[comp] + v);
+        const T out = (T)((double)old[comp] + v);
+        d[comp * n3d] = out;
+        if constexpr (ZEL) {
+            const uint64_t idx = comp * n3d + (uint64_t)row * nd + z;
+            zel_point<T>(out, comp == 0 ? x : (comp == 1 ? y : z), pv.origin[comp], pv.cell, pv.offset, pv.wrap,
+                         (T)pv.vfac, pos[idx], vel[idx]);
+        }
     }
 }
 

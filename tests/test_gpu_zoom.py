@@ -169,6 +169,28 @@ def test_zoom_graph_replays_match_eager():
     z.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_zoom_level_particles_equal_zeldovich_at(dtype):
+    # a level's particles come out of the interpolation pass; they must be
+    # what gg_zeldovich_at makes of the level's final displacements
+    n0, box0 = 64, 100.0
+    sizes, origins = [96, 64], [(50, 3, 17), (30, 36, 26)]
+    z = gg.Zoom(n0, box0, sizes, origins, dtype=dtype)
+    z.run(13)
+    torch.cuda.synchronize()
+    for l in range(1, len(z.levels)):
+        geo, lv = z.geometry[l], z.levels[l]
+        n = lv["w"].shape[0]
+        p = gg.Plan(n, geo["box"], gg.Cosmo(), dtype=dtype)
+        pos, vel = p.zeldovich_at(lv["psi"], geo["origin"], box0)
+        torch.cuda.synchronize()
+        say(f"[zoom] level {l} {dtype}: fused particles vs gg_zeldovich_at")
+        assert torch.equal(pos.view(torch.int32), lv["pos"].view(torch.int32))
+        assert torch.equal(vel.view(torch.int32), lv["vel"].view(torch.int32))
+        p.close()
+    z.close()
+
+
 def test_zoom_rejects_bad_descriptions():
     with pytest.raises(gg.GGError):
         gg.Zoom(64, 100.0, [100], [(0, 0, 0)])  # unsupported size
