@@ -442,10 +442,12 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zinv(const cx<T>* 
 // way into LDS (its tau carries no s_2).  PV: write positions and
 // velocities; PS: write the displacements in the path's type.
 //
-// The grid is smaller than the tile count: work-group b takes tiles b, b + G,
-// b + 2G, ... (G = gridDim.x).  As soon as a tile sits in LDS, each thread
-// loads its share of the next tile into registers, so those HBM reads run
-// under the current tile's transform and stores.  The N-point twiddle table
+// The grid is smaller than the tile count: work-group b takes every G-th tile
+// of its range (G = gridDim.x / 8 and the range its XCD's eighth of the
+// tiles when the grid is a multiple of 8, else G = gridDim.x over all
+// tiles).  As soon as a tile sits in LDS, each thread loads its share of the
+// next tile into registers, so those HBM reads run under the current tile's
+// transform and stores.  The N-point twiddle table
 // is copied into LDS once per work-group, so that the loop issues no other
 // global load (loads complete in order: waiting for a later one would wait
 // for the prefetch too).  The prefetch after the last tile re-reads that
@@ -486,9 +488,23 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* _
         }
     };
     const uint64_t n3 = (uint64_t)N * N * N;
-    int tile = blockIdx.x;
-    if (tile < ntiles) load(tile);
-    for (; tile < ntiles; tile += gridDim.x) {
+    // work-group b runs on XCD b % 8: with a grid of whole multiples of 8 each
+    // XCD takes one contiguous eighth of the tiles (fewer pages in flight per
+    // XCD), its work-groups striding through it
+    int tile, tend, step;
+    if ((gridDim.x & 7u) == 0) {
+        const int per = (ntiles + 7) / 8;
+        const int x = (int)(blockIdx.x & 7u);
+        tile = x * per + (int)(blockIdx.x >> 3);
+        tend = min(ntiles, (x + 1) * per);
+        step = (int)(gridDim.x >> 3);
+    } else {
+        tile = blockIdx.x;
+        tend = ntiles;
+        step = (int)gridDim.x;
+    }
+    if (tile < tend) load(tile);
+    for (; tile < tend; tile += step) {
         const int comp = tile / TPC;
         const uint64_t line0 = (uint64_t)(tile - comp * TPC) * L;
         // recomputed per tile rather than kept live across the loop
@@ -506,8 +522,8 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* _
             lds[lidx<L>(k, cc)] = x0;
             lds[lidx<L>(k + 1, cc)] = x1;
         }
-        const int next = tile + (int)gridDim.x;
-        load(next < ntiles ? next : tile);
+        const int next = tile + step;
+        load(next < tend ? next : tile);
         __syncthreads();
         cx<T> v[V];
 #pragma unroll
@@ -815,25 +831,27 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb2) = v[i];
         }
     } else {  // SMODE_YINV3
+        // G is loaded together with F: its reads are in flight during A's
+        // transform and stores (one work-group per compute unit, so nothing
+        // else would hide them)
+        cx<T> g[V];
         {
             const uint32_t lb = lane_bytes(j);
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RM, j, lb);
+#pragma unroll
+            for (int i = 0; i < V; ++i) g[i] = *at(a.in1, i, RM, j, lb);
             fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, c, j);
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < V; ++i) *at(a.out0, i, RL, j, lb) = v[i];
             }
         }
-        cx<T> g[V];
         {
             const int jj = opaque(j), cc = opaque(c);
             const uint32_t lb = lane_bytes(jj);
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-                g[i] = *at(a.in1, i, RM, jj, lb);
-                v[i] = cscale(g[i], (T)signed_mode(first_pos<N, 1>(jj, i), N));
-            }
+            for (int i = 0; i < V; ++i) v[i] = cscale(g[i], (T)signed_mode(first_pos<N, 1>(jj, i), N));
             fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);
             if (valid) {
 #pragma unroll

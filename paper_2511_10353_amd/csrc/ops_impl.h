@@ -249,10 +249,10 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
         StridedArgs<T> a2 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
         const StridedArgs<T> a3 = strided_args<T>(b0, nullptr, b1, b2, nullptr, 8 * M, 0, 0, 0, H, M, M);
         StridedArgs<T> a4 = strided_args<T>(b1, b2, b1, b0, b2, H, M, 3, 8 * M, 0, 0, M);
-        // XCD tile orders measured best at 1024^3: P2 one range per XCD, P3 pairs,
-        // P4 pairs (float) or one range per XCD (double)
+        // XCD tile orders measured best at 1024^3: P2 and P4 one range per XCD,
+        // P3 pairs
         a2.xgroup = 0;
-        a4.xgroup = sizeof(T) == 8 ? 0 : 2;
+        a4.xgroup = 0;
         const int xh = (N / 8) / NC;                           // m0 / 8 values per slab
         const int nb = ((M + Tile<T>::L - 1) / Tile<T>::L) / NC;  // column blocks per chunk
         if (NC > 1) {
