@@ -578,8 +578,8 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* _
 //   SMODE_XFILT (P3)      : axis 0, o = k1: in0 -> F (out0), G (out1)
 //   SMODE_YINV3 (P4)      : axis 1, o = m0: F (in0) -> A (out0), G (in1) -> B (out1), C (out2)
 //   SMODE_XADJ (A3)       : adjoint of P3 + P4's axis-0 work: forward transforms of
-//                           in0, in1, in2 (component spectra of the gradient),
-//                           S = -i tau (s0 X0 + s1 X1 + s2 X2), inverse -> out0
+//                           in0 and of s1 in1 + s2 in2 (component spectra of the
+//                           gradient), S = -i tau (s0 X0 + s1 X1 + s2 X2), inverse -> out0
 //   SMODE_XDELTA          : axis 0, o = k1: forward of in0, Eq. (1) factor
 //                           sqrt(P N^3 / L^3) / N^3 = tau n^2 k_f, inverse -> out0
 // A thread keeps one line's registers only: where a second transform of the
@@ -734,24 +734,32 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         const int s1 = signed_mode(o, N);
         const int s2 = col;
         const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
+        // s1 and s2 are constant along an axis-0 line, so s1 X1 + s2 X2 is
+        // formed before the transform: two forward transforms instead of three.
+        // X1 and X2 are loaded together, then X0 while their sum is transformed.
         cx<T> acc[V];
+        {
+            const uint32_t lb = lane_bytes(j);
 #pragma unroll
-        for (int i = 0; i < V; ++i) acc[i] = {(T)0, (T)0};
-#pragma unroll 1
-        for (int comp = 0; comp < 3; ++comp) {
+            for (int i = 0; i < V; ++i) v[i] = *at(a.in1, i, RF, j, lb);
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc[i] = *at(a.in2, i, RF, j, lb);
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = cadd(cscale(v[i], (T)s1), cscale(acc[i], (T)s2));
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc[i] = *at(a.in0, i, RF, j, lb);
+        }
+        {
             const int jj = opaque(j), cc = opaque(c);
-            const uint32_t lb = lane_bytes(jj);
-            const cx<T>* src = comp == 0 ? a.in0 : (comp == 1 ? a.in1 : a.in2);
-#pragma unroll
-            for (int i = 0; i < V; ++i) v[i] = *at(src, i, RF, jj, lb);
             fft_lines<T, N, L, -1, 1, RX>(v, lds, pv.tw, cc, jj);
+        }
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            fft_lines<T, N, L, -1, 1, RX>(acc, lds, pv.tw, cc, jj);
             const int jk = opaque(jj);
-            const T sc = (T)(comp == 1 ? s1 : s2);
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-                const T s = comp == 0 ? (T)signed_mode(last_pos<N, -1>(jk, i), N) : sc;
-                acc[i] = cadd(acc[i], cscale(v[i], s));
-            }
+            for (int i = 0; i < V; ++i)
+                acc[i] = cadd(cscale(acc[i], (T)signed_mode(last_pos<N, -1>(jk, i), N)), v[i]);
         }
         {
             const int jj = opaque(j), cc = opaque(c);
@@ -831,16 +839,20 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             for (int i = 0; i < V; ++i) *at(a.out0, i, RL, jj, lb2) = v[i];
         }
     } else {  // SMODE_YINV3
-        // G is loaded together with F: its reads are in flight during A's
-        // transform and stores (one work-group per compute unit, so nothing
-        // else would hide them)
+        // float tiles load G together with F: its reads are in flight during
+        // A's transform and stores (one work-group per compute unit, so nothing
+        // else would hide them); double tiles (two work-groups' worth of
+        // registers already) measured faster loading G after A
+        constexpr bool EARLY_G = sizeof(T) == 4;
         cx<T> g[V];
         {
             const uint32_t lb = lane_bytes(j);
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RM, j, lb);
+            if constexpr (EARLY_G) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) g[i] = *at(a.in1, i, RM, j, lb);
+                for (int i = 0; i < V; ++i) g[i] = *at(a.in1, i, RM, j, lb);
+            }
             fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, c, j);
             if (valid) {
 #pragma unroll
@@ -850,6 +862,10 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
         {
             const int jj = opaque(j), cc = opaque(c);
             const uint32_t lb = lane_bytes(jj);
+            if constexpr (!EARLY_G) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) g[i] = *at(a.in1, i, RM, jj, lb);
+            }
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = cscale(g[i], (T)signed_mode(first_pos<N, 1>(jj, i), N));
             fft_lines<T, N, L, 1, 1, RX>(v, lds, pv.tw, cc, jj);

@@ -363,17 +363,21 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
         if (dot) {
             GG_TRY(launch_dot_final(part, 3 * nblk, 0.5, g_log_amp, s))
         }
-        // A2: axis-1 forward of each component
+        // A2: axis-1 forward of each component (one contiguous tile range per
+        // XCD, as P2)
         const int64_t H = (int64_t)8 * N * M;
-        for (cx<T>* b : {b0, b1, b2})
-            GG_TRY((launch_strided<T, N, SMODE_FWD>(strided_args<T>(b, nullptr, b, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
-                                                    pv, s)))
+        for (cx<T>* b : {b0, b1, b2}) {
+            StridedArgs<T> a2 = strided_args<T>(b, nullptr, b, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
+            a2.xgroup = 0;
+            GG_TRY((launch_strided<T, N, SMODE_FWD>(a2, pv, s)))
+        }
         // A3: axis-0 forwards, -i tau sum_j s_j X_j, axis-0 inverse -> b0
         GG_TRY((launch_strided<T, N, SMODE_XADJ, true>(
             strided_args<T>(b0, b1, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M, b2), pv, s)))
         // A4: axis-1 inverse
-        GG_TRY((launch_strided<T, N, SMODE_INV>(strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M),
-                                                pv, s)))
+        StridedArgs<T> a4 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
+        a4.xgroup = 0;
+        GG_TRY((launch_strided<T, N, SMODE_INV>(a4, pv, s)))
         // A5: axis-2 c2r -> d loss / d W (the 1/N^3 is inside tau)
         k_zinv<T, N, true, LZ><<<N * N / LZ, LZ * PlanInfo<M>::TPL, 0, s>>>(b0, M, M, 0, gw, (T)1, pv);
         GG_TRY(hipGetLastError())
