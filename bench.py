@@ -234,8 +234,8 @@ def adjoint_bytes(n, elem, log_amp):
     n3 = n ** 3
     spec = n3 * elem
     out = [3 * n3 * elem + 3 * spec,   # A1: read g_psi, write three spectra
-           6 * spec,                   # A2: read + write three spectra
-           3 * spec + spec,            # A3: read three, write one
+           3 * spec + 2 * spec,        # A2: read three spectra, write two (Y0, s1 Y1 + s2 Y2)
+           2 * spec + spec,            # A3: read two, write one
            2 * spec,                   # A4
            spec + n3 * elem]           # A5: read one spectrum, write g_W
     if log_amp:

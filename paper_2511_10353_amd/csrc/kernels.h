@@ -577,16 +577,28 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* _
 //   SMODE_FWD / SMODE_INV : in0 -> out0 (may alias), forward / unnormalised inverse
 //   SMODE_XFILT (P3)      : axis 0, o = k1: in0 -> F (out0), G (out1)
 //   SMODE_YINV3 (P4)      : axis 1, o = m0: F (in0) -> A (out0), G (in1) -> B (out1), C (out2)
+//   SMODE_YADJ (A2)       : axis 1, o = m0: forward transforms of two of the
+//                           gradient's component spectra, Z = s1 FFT1(in0) + s2 FFT1(in1)
+//                           -> out0 (the first, Y0, is a SMODE_FWD pass)
 //   SMODE_XADJ (A3)       : adjoint of P3 + P4's axis-0 work: forward transforms of
-//                           in0 and of s1 in1 + s2 in2 (component spectra of the
-//                           gradient), S = -i tau (s0 X0 + s1 X1 + s2 X2), inverse -> out0
+//                           in0 (Y0) and in1 (Z), S = -i tau (s0 FFT0(Y0) + FFT0(Z))
+//                           = -i tau (s0 X0 + s1 X1 + s2 X2), inverse -> out0
 //   SMODE_XDELTA          : axis 0, o = k1: forward of in0, Eq. (1) factor
 //                           sqrt(P N^3 / L^3) / N^3 = tau n^2 k_f, inverse -> out0
 // A thread keeps one line's registers only: where a second transform of the
 // same input is needed, the tile is read again (the re-read is served by the
 // caches) rather than held, which keeps the kernels free of register spills.
 // ---------------------------------------------------------------------------
-enum { SMODE_FWD = 0, SMODE_INV = 1, SMODE_XFILT = 2, SMODE_YINV3 = 3, SMODE_XADJ = 4, SMODE_XDELTA = 5, SMODE_XWIN = 6 };
+enum {
+    SMODE_FWD = 0,
+    SMODE_INV = 1,
+    SMODE_XFILT = 2,
+    SMODE_YINV3 = 3,
+    SMODE_XADJ = 4,
+    SMODE_XDELTA = 5,
+    SMODE_XWIN = 6,
+    SMODE_YADJ = 7
+};
 
 template <typename T>
 struct StridedArgs {
@@ -728,24 +740,46 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
                 for (int i = 0; i < V; ++i) *at(a.out1, i, RL, jj, lb2) = g[i];
             }
         }
+    } else if constexpr (MODE == SMODE_YADJ) {
+        // Z = s1 FFT1(in0) + s2 FFT1(in1) -> out0
+        cx<T> g[V];
+        {
+            const uint32_t lb = lane_bytes(j);
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = *at(a.in0, i, RF, j, lb);
+            fft_lines<T, N, L, -1, 1, RX>(v, lds, pv.tw, c, j);
+            const int jk = opaque(j);
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = cscale(v[i], (T)signed_mode(last_pos<N, -1>(jk, i), N));
+        }
+        {
+            const int jj = opaque(j), cc = opaque(c);
+            const uint32_t lb = lane_bytes(jj);
+#pragma unroll
+            for (int i = 0; i < V; ++i) g[i] = *at(a.in1, i, RF, jj, lb);
+            fft_lines<T, N, L, -1, 1, RX>(g, lds, pv.tw, cc, jj);
+            const T s2 = (T)col;
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = cadd(v[i], cscale(g[i], s2));
+            const uint32_t lb2 = lane_bytes(jj);
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) *at(a.out0, i, RM, jj, lb2) = v[i];
+            }
+        }
     } else if constexpr (MODE == SMODE_XADJ) {
         const TauLookup<T> taul = tau_lookup(pv);
         __syncthreads();
         const int s1 = signed_mode(o, N);
         const int s2 = col;
         const bool line_zero = (s1 == -(N / 2)) || (s2 >= N / 2);
-        // s1 and s2 are constant along an axis-0 line, so s1 X1 + s2 X2 is
-        // formed before the transform: two forward transforms instead of three.
-        // X1 and X2 are loaded together, then X0 while their sum is transformed.
+        // A2 has already formed Z = s1 Y1 + s2 Y2 (s1 and s2 are constant along
+        // an axis-0 line): two forward transforms, Z and Y0 loaded together
         cx<T> acc[V];
         {
             const uint32_t lb = lane_bytes(j);
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = *at(a.in1, i, RF, j, lb);
-#pragma unroll
-            for (int i = 0; i < V; ++i) acc[i] = *at(a.in2, i, RF, j, lb);
-#pragma unroll
-            for (int i = 0; i < V; ++i) v[i] = cadd(cscale(v[i], (T)s1), cscale(acc[i], (T)s2));
 #pragma unroll
             for (int i = 0; i < V; ++i) acc[i] = *at(a.in0, i, RF, j, lb);
         }

@@ -363,17 +363,18 @@ hipError_t Ops<T>::adjoint(const PlanView<T>& pv, const T* gpsi, const float* gp
         if (dot) {
             GG_TRY(launch_dot_final(part, 3 * nblk, 0.5, g_log_amp, s))
         }
-        // A2: axis-1 forward of each component (one contiguous tile range per
-        // XCD, as P2)
+        // A2: axis-1 forwards of the three components: Y0 -> b0 and
+        // Z = s1 Y1 + s2 Y2 -> b1 (one contiguous tile range per XCD, as P2)
         const int64_t H = (int64_t)8 * N * M;
-        for (cx<T>* b : {b0, b1, b2}) {
-            StridedArgs<T> a2 = strided_args<T>(b, nullptr, b, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
-            a2.xgroup = 0;
-            GG_TRY((launch_strided<T, N, SMODE_FWD>(a2, pv, s)))
-        }
-        // A3: axis-0 forwards, -i tau sum_j s_j X_j, axis-0 inverse -> b0
+        StridedArgs<T> a2 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
+        a2.xgroup = 0;
+        GG_TRY((launch_strided<T, N, SMODE_FWD>(a2, pv, s)))
+        StridedArgs<T> a2z = strided_args<T>(b1, b2, b1, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
+        a2z.xgroup = 0;
+        GG_TRY((launch_strided<T, N, SMODE_YADJ>(a2z, pv, s)))
+        // A3: axis-0 forwards of Y0 and Z, -i tau (s0 X0 + Z'), axis-0 inverse -> b0
         GG_TRY((launch_strided<T, N, SMODE_XADJ, true>(
-            strided_args<T>(b0, b1, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M, b2), pv, s)))
+            strided_args<T>(b0, b1, b0, nullptr, nullptr, 8 * M, 0, 0, 0, H, M, M), pv, s)))
         // A4: axis-1 inverse
         StridedArgs<T> a4 = strided_args<T>(b0, nullptr, b0, nullptr, nullptr, H, M, 3, 8 * M, 0, 0, M);
         a4.xgroup = 0;
