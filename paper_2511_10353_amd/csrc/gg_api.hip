@@ -281,8 +281,8 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     hipStream_t s = nullptr;
     gg_status st = GG_OK;
     auto cleanup = [&]() {
-        if (d_sig) hipFree(d_sig);
-        if (s) hipStreamDestroy(s);
+        if (d_sig) (void)hipFree(d_sig);
+        if (s) (void)hipStreamDestroy(s);
     };
     do {
         if ((e = hipMalloc(&p->tw, 2 * es * p->n)) != hipSuccess ||
@@ -370,11 +370,11 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
     cleanup();
     if (st != GG_OK) {
         for (hipEvent_t ev : p->sync)
-            if (ev) hipEventDestroy(ev);
-        if (p->aux) hipStreamDestroy(p->aux);
-        if (p->tw) hipFree(p->tw);
-        if (p->tau) hipFree(p->tau);
-        if (p->tauseg) hipFree(p->tauseg);
+            if (ev) (void)hipEventDestroy(ev);
+        if (p->aux) (void)hipStreamDestroy(p->aux);
+        if (p->tw) (void)hipFree(p->tw);
+        if (p->tau) (void)hipFree(p->tau);
+        if (p->tauseg) (void)hipFree(p->tauseg);
         delete p;
         return st;
     }
@@ -385,17 +385,17 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
 gg_status gg_plan_destroy(gg_plan* p) {
     if (!p) return GG_OK;
     int cur = -1;
-    hipGetDevice(&cur);
-    if (cur != p->device) hipSetDevice(p->device);
-    hipDeviceSynchronize();
-    for (hipEvent_t ev : p->events) hipEventDestroy(ev);
+    (void)hipGetDevice(&cur);
+    if (cur != p->device) (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t ev : p->events) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : p->sync)
-        if (ev) hipEventDestroy(ev);
-    if (p->aux) hipStreamDestroy(p->aux);
-    if (p->tw) hipFree(p->tw);
-    if (p->tau) hipFree(p->tau);
-    if (p->tauseg) hipFree(p->tauseg);
-    if (cur >= 0 && cur != p->device) hipSetDevice(cur);
+        if (ev) (void)hipEventDestroy(ev);
+    if (p->aux) (void)hipStreamDestroy(p->aux);
+    if (p->tw) (void)hipFree(p->tw);
+    if (p->tau) (void)hipFree(p->tau);
+    if (p->tauseg) (void)hipFree(p->tauseg);
+    if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete p;
     return GG_OK;
 }
@@ -995,7 +995,7 @@ gg_status gg_plan_autotune(gg_plan* p, float* pos, float* vel, void* work, int32
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) {
-        if (t0) hipEventDestroy(t0);
+        if (t0) (void)hipEventDestroy(t0);
         return fail_hip(e, "hipEventCreate");
     }
     const int keep_c = p->nchunk, keep_1 = p->p1_lines, keep_z = p->z_lines;
@@ -1030,8 +1030,8 @@ gg_status gg_plan_autotune(gg_plan* p, float* pos, float* vel, void* work, int32
                     bz = lz;
                 }
             }
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
     if (st != GG_OK || e != hipSuccess) {
         p->nchunk = keep_c;
         p->p1_lines = keep_1;
@@ -1128,12 +1128,12 @@ constexpr int kEvEnd = 1 + GG_ZOOM_MAX_LEVELS;
 
 void zoom_free(gg_zoom* z) {
     if (!z) return;
-    if (z->exec) hipGraphExecDestroy(z->exec);
-    if (z->graph) hipGraphDestroy(z->graph);
+    if (z->exec) (void)hipGraphExecDestroy(z->exec);
+    if (z->graph) (void)hipGraphDestroy(z->graph);
     for (hipEvent_t e : z->ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (hipStream_t st : z->side)
-        if (st) hipStreamDestroy(st);
+        if (st) (void)hipStreamDestroy(st);
     for (gg_plan* p : z->plans) gg_plan_destroy(p);
     delete z;
 }
@@ -1216,8 +1216,8 @@ gg_status gg_zoom_create(gg_zoom** out, const gg_zoom_desc* d, const gg_cosmo* c
 
 gg_status gg_zoom_destroy(gg_zoom* z) {
     if (!z) return GG_OK;
-    if (!z->plans.empty()) hipSetDevice(z->plans[0]->device);
-    hipDeviceSynchronize();
+    if (!z->plans.empty()) (void)hipSetDevice(z->plans[0]->device);
+    (void)hipDeviceSynchronize();
     zoom_free(z);
     return GG_OK;
 }
@@ -1237,7 +1237,7 @@ gg_status gg_zoom_autotune(gg_zoom* z, uint64_t seed, void* const* w, void* cons
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) {
-        if (t0) hipEventDestroy(t0);
+        if (t0) (void)hipEventDestroy(t0);
         return fail_hip(e, "hipEventCreate");
     }
     auto time_run = [&](double& ms_out) -> gg_status {
@@ -1287,15 +1287,15 @@ gg_status gg_zoom_autotune(gg_zoom* z, uint64_t seed, void* const* w, void* cons
         p->p1_lines = st == GG_OK ? b1 : keep_1;
         p->z_lines = st == GG_OK ? bz : keep_z;
     }
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
     // a graph captured before holds the old launch shapes
     if (z->exec) {
-        hipGraphExecDestroy(z->exec);
+        (void)hipGraphExecDestroy(z->exec);
         z->exec = nullptr;
     }
     if (z->graph) {
-        hipGraphDestroy(z->graph);
+        (void)hipGraphDestroy(z->graph);
         z->graph = nullptr;
     }
     if (st != GG_OK) return st;
@@ -1453,11 +1453,11 @@ gg_status gg_zoom_run(gg_zoom* z, uint64_t seed, void* const* w, void* const* ps
     key.push_back(stream);
     if (!z->exec || key != z->key || seed != z->key_seed) {
         if (z->exec) {
-            hipGraphExecDestroy(z->exec);
+            (void)hipGraphExecDestroy(z->exec);
             z->exec = nullptr;
         }
         if (z->graph) {
-            hipGraphDestroy(z->graph);
+            (void)hipGraphDestroy(z->graph);
             z->graph = nullptr;
         }
         if (s == nullptr) return fail(GG_ERR_INVALID_ARG, "graph capture needs a non-null stream");
@@ -1467,13 +1467,13 @@ gg_status gg_zoom_run(gg_zoom* z, uint64_t seed, void* const* w, void* const* ps
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s, &g);
         if (st != GG_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return st;
         }
         if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&z->exec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             return fail_hip(e, "hipGraphInstantiate");
         }
         z->graph = g;

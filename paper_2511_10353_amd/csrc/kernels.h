@@ -535,7 +535,8 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zel(const cx<T>* _
         __syncthreads();
         // float tiles: a rolled loop keeps the kernel within 64 registers (two
         // work-groups per compute unit); double tiles are bound by LDS anyway
-#pragma unroll(sizeof(T) == 8 ? NF : 1)
+        constexpr int STORE_UNROLL = sizeof(T) == 8 ? NF : 1;
+#pragma unroll STORE_UNROLL
         for (int q = 0; q < NF; ++q) {
             const int fi = t + q * NT;
             const int cc = fi / (M / 2), m = 2 * (fi % (M / 2));

@@ -188,8 +188,8 @@ hipError_t Ops<T>::zeldovich(const PlanView<T>& pv, const T* psi, float* pos, fl
 
 template <typename T>
 void Ops<T>::tile_options(int n, int& full, int& half, int& p1_default, int& z_default) {
-    full = half = p1_default = z_default = 0;
-    dispatch_n(n, [&](auto nc) -> hipError_t {
+    full = half = p1_default = z_default = 0;  // left at 0 for a size without a plan
+    (void)dispatch_n(n, [&](auto nc) -> hipError_t {
         constexpr int N = decltype(nc)::value;
         full = ZLines<T, N>::L;
         half = full / 2 >= 1 ? full / 2 : 1;
