@@ -173,7 +173,8 @@ def _check_ic(n, box, seed, dtype, pos, vel, psi):
     assert pos.min() >= 0 and pos.max() < box
 
 
-@pytest.mark.parametrize("n,box,dtype", [(32, 100.0, "f64"), (32, 100.0, "f32"), (64, 100.0, "f32"),
+@pytest.mark.parametrize("n,box,dtype", [(8, 40.0, "f32"), (8, 40.0, "f64"), (16, 60.0, "f32"),
+                                         (32, 100.0, "f64"), (32, 100.0, "f32"), (64, 100.0, "f32"),
                                          (96, 112.5, "f32"), (96, 112.5, "f64"), (160, 46.875, "f32"),
                                          (160, 46.875, "f64"), (192, 112.5, "f32"), (192, 112.5, "f64"),
                                          (256, 500.0, "f32"), (256, 500.0, "f64")])
