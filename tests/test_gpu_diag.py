@@ -48,10 +48,12 @@ def test_density_from_seed_against_oracle(dtype, n):
 def test_density_from_field_equals_seed_path(dtype):
     n, box = 64, 200.0
     p = _plan(n, box, dtype)
-    a = p.make_density(7)
-    b = p.make_density(w=p.noise(7))
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    for seed in (7, 2**64 - 1):
+        # the first pass's own noise equals gg_noise's, bit for bit
+        a = p.make_density(seed)
+        b = p.make_density(w=p.noise(seed))
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), seed
 
 
 def test_density_is_minus_divergence_of_displacements():

@@ -41,7 +41,7 @@ def test_plan_normalisation_matches_oracle():
 @pytest.mark.parametrize("n", [8, 16, 32, 64])
 def test_noise_bit_exact_small(n, dtype):
     p = _plan(n, 100.0, dtype)
-    for seed, stream in ((42, 0), (2**63 + 12345, 7)):
+    for seed, stream in ((42, 0), (2**63 + 12345, 7), (0, 0), (2**64 - 1, 2**32 - 1)):
         got = p.noise(seed, stream_id=stream).cpu().numpy()
         want = onoise.noise_grid(n, seed, stream, dtype=NPDT[dtype])
         assert got.tobytes() == want.tobytes()
