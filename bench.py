@@ -327,7 +327,21 @@ def cpu_baseline(n=256, box=500.0, min_seconds=10.0, max_reps=6):
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+            info = {}
+            for ln in f:
+                if ":" in ln:
+                    k, v = ln.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
+                if not ln.strip() and info:
+                    break  # the first processor's block
+        model = info.get("model name", "")
+        extra = [f"family {info['cpu family']}" if "cpu family" in info else "",
+                 f"model {info['model']}" if "model" in info else "",
+                 f"stepping {info['stepping']}" if "stepping" in info else "",
+                 "avx512" if "avx512f" in info.get("flags", "").split() else ""]
+        extra = ", ".join(e for e in extra if e)
+        if extra:
+            model = f"{model} ({extra})"
     except OSError:
         pass
     return {"value": round(reps * n ** 3 / dt, 1), "unit": "cells/s", "cores": cores, "kind": "oracle",
