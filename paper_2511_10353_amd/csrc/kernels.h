@@ -742,7 +742,14 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             }
         }
     } else if constexpr (MODE == SMODE_YADJ) {
-        // Z = s1 FFT1(in0) + s2 FFT1(in1) -> out0
+        // Z = s1 FFT1(in0) + s2 FFT1(in1) -> out0.  At N = 1024, while the second
+        // line is transformed, PK of the first line's values wait in the LDS
+        // left over beside the tile (its registers would spill otherwise; smaller
+        // plans fit, and extra LDS would cost them work-groups per CU)
+        constexpr int NT = L * TPL;
+        constexpr int FREE = (160 * 1024 - (int)sizeof(cx<T>) * L * N) / ((int)sizeof(cx<T>) * NT);
+        constexpr int PK = N < 1024 ? 0 : (FREE < V ? FREE : V);
+        __shared__ cx<T> park[(PK > 0 ? PK : 1) * NT];
         cx<T> g[V];
         {
             const uint32_t lb = lane_bytes(j);
@@ -752,6 +759,9 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
             const int jk = opaque(j);
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = cscale(v[i], (T)signed_mode(last_pos<N, -1>(jk, i), N));
+            const int tt = opaque((int)threadIdx.x);
+#pragma unroll
+            for (int i = 0; i < PK; ++i) park[i * NT + tt] = v[V - PK + i];
         }
         {
             const int jj = opaque(j), cc = opaque(c);
@@ -759,6 +769,9 @@ __global__ __launch_bounds__(L * PlanInfo<N>::TPL) void k_strided(StridedArgs<T>
 #pragma unroll
             for (int i = 0; i < V; ++i) g[i] = *at(a.in1, i, RF, jj, lb);
             fft_lines<T, N, L, -1, 1, RX>(g, lds, pv.tw, cc, jj);
+            const int tt = opaque((int)threadIdx.x);
+#pragma unroll
+            for (int i = 0; i < PK; ++i) v[V - PK + i] = park[i * NT + tt];
             const T s2 = (T)col;
 #pragma unroll
             for (int i = 0; i < V; ++i) v[i] = cadd(v[i], cscale(g[i], s2));
