@@ -53,7 +53,9 @@ struct gg_plan {
     void* tw = nullptr;    // N complex values of the dtype
     void* tau = nullptr;   // ntau values of the dtype
     int64_t ntau = 0;
-    void* tauseg = nullptr;  // piecewise tau: kTauSeg float4 (float plans), kTauSeg64 x 8 doubles (double plans)
+    // piecewise tau: kTauSeg float4 followed by the noise's logarithm table
+    // (kLnTab double2) for float plans, kTauSeg64 x 8 doubles for double plans
+    void* tauseg = nullptr;
     double amplitude = 0, sigma_int = 0, growth = 0, vfac = 0, cell = 0;
     // tile choices of the fused path (0 = built-in; set by gg_plan_set_tuning
     // or gg_plan_autotune)
@@ -150,6 +152,9 @@ gg::PlanView<T> view(const gg_plan* p) {
     v.tau = static_cast<const T*>(p->tau);
     v.tauseg = std::is_same_v<T, float> ? static_cast<const float4*>(p->tauseg) : nullptr;
     v.tauseg64 = std::is_same_v<T, double> ? static_cast<const double2*>(p->tauseg) : nullptr;
+    v.lntab = std::is_same_v<T, float> ? reinterpret_cast<const double2*>(static_cast<const char*>(p->tauseg) +
+                                                                       gg::kTauSeg * sizeof(float4))
+                                       : nullptr;
     v.amp_scale = 1.0;
     v.n2_lo = 0;
     v.n2_hi = 0x7FFFFFFF;
@@ -289,7 +294,7 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
             (e = hipMalloc(&p->tau, es * p->ntau)) != hipSuccess || (e = hipMalloc(&d_sig, sizeof(double))) != hipSuccess ||
             (e = fault_injected("plan_alloc")
                      ? hipErrorOutOfMemory
-                     : hipMalloc(&p->tauseg, dtype == GG_F32 ? gg::kTauSeg * sizeof(float4)
+                     : hipMalloc(&p->tauseg, dtype == GG_F32 ? gg::kTauSeg * sizeof(float4) + gg::kLnTab * sizeof(double2)
                                                              : gg::kTauSeg64 * (gg::kTauDeg64 + 1) * sizeof(double))) !=
                 hipSuccess) {
             st = fail(GG_ERR_OUT_OF_MEMORY, std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
@@ -305,7 +310,12 @@ gg_status gg_plan_create(gg_plan** out, const gg_grid* grid, const gg_cosmo* cos
             if (e == hipSuccess) e = hipStreamSynchronize(s);
         } else {
             auto tw = make_twiddles<float>(p->n);
+            std::array<double2, gg::kLnTab> lnt;
+            gg::make_ln_table(lnt.data());
             e = hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(tw[0]), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(static_cast<char*>(p->tauseg) + gg::kTauSeg * sizeof(float4), lnt.data(),
+                                   sizeof(lnt), hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
         }
         if (e != hipSuccess) {

@@ -43,6 +43,7 @@ struct PlanView {
     const T* tau;           // tau[n^2], n^2 <= 3 (N/2)^2, binary64 values rounded to T
     const float4* tauseg;   // piecewise-cubic tau (kTauSeg segments), float plans only
     const double2* tauseg64;  // piecewise degree-7 tau (kTauSeg64 x 4 double2), double plans only
+    const double2* lntab;   // logarithm table of the noise (kLnTab entries), float plans only
     double amp_scale;       // displacement scale sqrt(A'/A) (1 for the plan's amplitude)
     // mode window of the axis-0 filter passes (Eq. 4-5): modes with
     // n2 < n2_lo or n2 >= n2_hi are dropped; deconv divides by the
@@ -145,10 +146,17 @@ __device__ __forceinline__ int signed_mode(int k, int n) { return k < (n >> 1) ?
 // White noise, one cell per thread and iteration.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_noise(T* __restrict__ w, uint64_t ncells, uint64_t seed, uint32_t stream) {
+__global__ void k_noise(T* __restrict__ w, uint64_t ncells, uint64_t seed, uint32_t stream, const double2* lntab) {
+    const double2* lnt = nullptr;
+    if constexpr (std::is_same_v<T, float>) {
+        __shared__ double2 lt[kLnTab];
+        for (int i = threadIdx.x; i < kLnTab; i += blockDim.x) lt[i] = lntab[i];
+        __syncthreads();
+        lnt = lt;
+    }
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
          c += (uint64_t)gridDim.x * blockDim.x)
-        w[c] = noise_value<T>(c, seed, stream);
+        w[c] = noise_value<T>(c, seed, stream, lnt);
 }
 
 // Lattice coordinates (m0, m1) of spectrum row r.  Plain rows are r = m0 N + m1;
@@ -217,6 +225,8 @@ struct ZSrc {
     // k2 < kout are written, kout per line (a pruned half spectrum)
     uint64_t wstride_comp;
     int kout;
+    // ZSRC_NOISE of float plans: the logarithm table of the noise
+    const double2* lntab = nullptr;
 };
 
 template <typename T, int N, int SRC, bool NYQ, bool BLK, int L = Tile<T>::L>
@@ -235,6 +245,13 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
     const uint64_t line0 = row0 + (uint64_t)blockIdx.x * L;
 
     if constexpr (SRC == ZSRC_NOISE) {
+        const double2* lnt = nullptr;
+        if constexpr (std::is_same_v<T, float>) {
+            __shared__ double2 lt[kLnTab];
+            for (int i = t; i < kLnTab; i += NT) lt[i] = zs.lntab[i];
+            __syncthreads();
+            lnt = lt;
+        }
         // complex slot p of a line holds cells 2p, 2p+1; sixteen lanes fill one
         // slot row of the tile (sixteen lines)
         for (int si = t; si < L * M; si += NT) {
@@ -242,7 +259,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
             int m0, m1;
             row_coords<BLK>(line0 + cc, N, m0, m1);
             const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * p;
-            lds[lidx<L>(p, cc)] = {noise_value<T>(cell, seed, stream), noise_value<T>(cell + 1, seed, stream)};
+            lds[lidx<L>(p, cc)] = {noise_value<T>(cell, seed, stream, lnt), noise_value<T>(cell + 1, seed, stream, lnt)};
         }
     } else {
         // four consecutive reals (two packed complex slots) per lane

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <cstring>
 #include <type_traits>
 
 namespace gg {
@@ -136,32 +138,61 @@ __device__ __forceinline__ double gaussian_cell(uint64_t c, uint64_t seed, uint3
     return gaussian_words(w.x, w.y);
 }
 
-// The same deviate to about 2^-46 relative, for the float path: the
-// exponent split by frexp, the atanh series to t^16 with a reciprocal
-// estimate refined by one Newton step, the square root by a reciprocal
+// Logarithm table of the float path.  A positive double u is written
+// u = 2^k z with z in [kLnTabLo, 2 kLnTabLo) (about [0.709, 1.418)) by
+// integer arithmetic on its bits: t = bits(u) - bits(kLnTabLo), k = t >> 52
+// (arithmetic), bits(z) = bits(u) - k 2^52.  Bits 45..51 of t select one of
+// 128 buckets of z, equal in bit space (2^-8 wide below 1, 2^-7 above).
+// Entry i is (invc, 2 ln invc) for an inverse centre invc of bucket i, so
+// that ln u = k ln 2 - ln invc + ln(1 + r) with r = z invc - 1, |r| < 2^-8.
+// kLnTabLo is placed so that 1 lies in the middle of its bucket, whose entry
+// is (1, 0): near u = 1 the logarithm is ln(1 + r) with r = z - 1 exact, and
+// next to that bucket |ln z| > 2^-9.5, so the cancellation of 2 ln invc
+// against 2 ln(1 + r) costs at most a factor of about 2.
+constexpr int kLnTabBits = 7;
+constexpr int kLnTab = 1 << kLnTabBits;
+constexpr uint64_t kLnTabLoBits = 0x3FF0000000000000ull - (uint64_t)(2 * 74 + 1) * (1ull << (51 - kLnTabBits));
+
+// Host side: fills t[0 .. kLnTab) (x = invc, y = 2 ln invc).  invc is the
+// reciprocal of the bucket's midpoint in value; the logarithm comes from the
+// host's libm (within an ulp or so), far inside the float path's 2^-46.
+inline void make_ln_table(double2* t) {
+    const uint64_t one = 0x3FF0000000000000ull;
+    for (int i = 0; i < kLnTab; ++i) {
+        const uint64_t lo = kLnTabLoBits + ((uint64_t)i << (52 - kLnTabBits));
+        const uint64_t hi = lo + (1ull << (52 - kLnTabBits));
+        double zlo, zhi;
+        std::memcpy(&zlo, &lo, sizeof zlo);
+        std::memcpy(&zhi, &hi, sizeof zhi);
+        const double invc = (lo <= one && one < hi) ? 1.0 : 2.0 / (zlo + zhi);
+        t[i] = make_double2(invc, 2.0 * std::log(invc));
+    }
+}
+
+// The same deviate to about 2^-46 relative, for the float path: -2 ln u1
+// from the table above and ln(1 + r) to r^6 (truncation below 2^-50 of the
+// result, also next to the bucket of 1), the square root by a reciprocal
 // square root estimate and one Goldschmidt step, and cos(2 pi u2) as
 // +-sin(2 pi n 2^-32) with n in [0, 2^30] (cos(alpha) = sin(pi/2 - alpha)
 // taken on the integer angle, so one odd Taylor series to x^19 covers every
-// quadrant; truncation below 2^-51 on [0, pi/2]).  The hardware estimates
-// are good to about 2^-24, so each refinement leaves about 2^-47.  u1, m and
-// e are the same exact values the defining sequence forms; r = -0 when
-// -2 ln u1 = 0, as sqrt(-0) gives there.
-__device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1) {
+// quadrant; truncation below 2^-51 on [0, pi/2]).  The hardware estimate is
+// good to about 2^-24, so the refinement leaves about 2^-47.  u1 is the exact
+// value the defining sequence forms; r = -0 when -2 ln u1 = 0, as sqrt(-0)
+// gives there.  lnt: the table, in LDS.
+__device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1, const double2* lnt) {
     const double u1 = fma((double)w0, kTwoM32, kTwoM32);  // (w0 + 1) 2^-32, exact
-    const double f = __builtin_amdgcn_frexp_mant(u1);     // u1 = f 2^e, f in [1/2, 1)
-    int e = __builtin_amdgcn_frexp_exp(u1);
-    const bool low = f < kSqrtHalfD;
-    const double m = low ? f * 2.0 : f;
-    e -= low ? 1 : 0;
-    const double den = m + 1.0;
-    double rc = __builtin_amdgcn_rcp(den);
-    rc = fma(rc, fma(-den, rc, 1.0), rc);
-    const double t = (m - 1.0) * rc;
-    const double s = t * t;
-    double p = atanh_coeff(8);
-#pragma unroll
-    for (int k = 7; k >= 0; --k) p = fma(p, s, atanh_coeff(k));
-    const double a = fma((double)e, -2.0 * kLn2, -4.0 * (t * p));  // -2 ln u1 >= 0
+    const uint64_t ix = (uint64_t)__double_as_longlong(u1);
+    const uint64_t tb = ix - kLnTabLoBits;
+    const int k = (int)((int64_t)tb >> 52);
+    const double2 ent = lnt[(uint32_t)(tb >> (52 - kLnTabBits)) & (kLnTab - 1)];
+    const double z = __longlong_as_double((long long)(ix - ((uint64_t)(int64_t)k << 52)));
+    const double r0 = fma(z, ent.x, -1.0);
+    double p = fma(r0, 1.0 / 6.0, -1.0 / 5.0);
+    p = fma(p, r0, 1.0 / 4.0);
+    p = fma(p, r0, -1.0 / 3.0);
+    p = fma(p, r0, 1.0 / 2.0);
+    const double lp = fma(-(r0 * r0), p, r0);  // ln(1 + r0)
+    const double a = fma(lp, -2.0, fma((double)k, -2.0 * kLn2, ent.y));  // -2 ln u1 >= 0
     const double y = __builtin_amdgcn_rsq(a);
     const double g0 = a * y, h0 = 0.5 * y;
     const double rr = fma(-g0, h0, 0.5);
@@ -170,10 +201,10 @@ __device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1) 
     const uint32_t rho = w1 & 0x3FFFFFFFu;
     const uint32_t n = (q & 1u) ? rho : (1u << 30) - rho;
     const double x = (double)n * (kTwoPi * kTwoM32);
-    const double z = x * x;
+    const double zz = x * x;
     double ps = sin_coeff(9);
 #pragma unroll
-    for (int k = 8; k >= 0; --k) ps = fma(ps, z, sin_coeff(k));
+    for (int j = 8; j >= 0; --j) ps = fma(ps, zz, sin_coeff(j));
     const double v = x * ps;
     return r * ((q == 1u || q == 2u) ? -v : v);
 }
@@ -187,11 +218,12 @@ __device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1) 
 // mantissa bits read 2^28, and 2^-42 |g| is below 2^11 units in the last
 // place of g, so g is safe when those bits are more than 2^11 from 2^28
 // (|g| > 2^-46 or g = 0 always, so float subnormals do not arise).
+// lnt: the float path's logarithm table in LDS (unused by the double path).
 template <typename T>
-__device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t stream) {
+__device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t stream, const double2* lnt) {
     const u32x4 w = cell_words(c, seed, stream);
     if constexpr (std::is_same_v<T, float>) {
-        const double g = gaussian_words_fast(w.x, w.y);
+        const double g = gaussian_words_fast(w.x, w.y, lnt);
         const uint32_t lo29 = (uint32_t)__double_as_longlong(g) & 0x1FFFFFFFu;
         if (__builtin_expect(lo29 - 0x10000000u + 2048u > 4096u, 1)) return (float)g;
         return (float)gaussian_words(w.x, w.y);

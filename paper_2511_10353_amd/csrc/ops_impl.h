@@ -128,7 +128,7 @@ hipError_t launch_xfilt(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStre
 template <typename T>
 hipError_t Ops<T>::noise(const PlanView<T>& pv, uint64_t seed, uint32_t stream_id, T* w, hipStream_t s) {
     const uint64_t n3 = (uint64_t)pv.n * pv.n * pv.n;
-    k_noise<T><<<capped_grid(n3, 256), 256, 0, s>>>(w, n3, seed, stream_id);
+    k_noise<T><<<capped_grid(n3, 256), 256, 0, s>>>(w, n3, seed, stream_id, pv.lntab);
     return hipGetLastError();
 }
 
@@ -272,7 +272,8 @@ hipError_t Ops<T>::fused_forward(const PlanView<T>& pv, const T* w, uint64_t see
                     k_zfwd<T, N, ZSRC_REAL, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw, 0,
                                                                                                       0u, row0);
                 } else {
-                    const ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+                    ZSrc<T> zs{nullptr, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+                    zs.lntab = pv.lntab;
                     k_zfwd<T, N, ZSRC_NOISE, false, true, L1><<<blocks, L1 * PlanInfo<M>::TPL, 0, sa>>>(zs, b0, pv.tw,
                                                                                                        seed, 0u, row0);
                 }
@@ -399,7 +400,8 @@ hipError_t Ops<T>::density(const PlanView<T>& pv, uint64_t seed, const T* w, T* 
 #define GG_TRY(expr) \
     if ((e = (expr)) != hipSuccess) return e;
         const int64_t H = (int64_t)8 * N * M;
-        const ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+        ZSrc<T> zs{w, nullptr, nullptr, nullptr, 0.0, 0, nullptr, nullptr};
+        zs.lntab = pv.lntab;
         if (w)
             k_zfwd<T, N, ZSRC_REAL, false, true, L1><<<N * N / L1, L1 * PlanInfo<M>::TPL, 0, s>>>(zs, b0, pv.tw, 0, 0u, 0);
         else
