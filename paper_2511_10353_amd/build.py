@@ -2,7 +2,8 @@
 
 Usage: python -m paper_2511_10353_amd.build   (or build() from Python).
 Every .hip file under csrc/ is compiled with hipcc into _build/, in parallel,
-and linked into paper_2511_10353_amd/libgg.so.
+and linked into paper_2511_10353_amd/libgg.so; probe/issue_probe.hip becomes the
+stand-alone issue-rate probe paper_2511_10353_amd/probe/issue_probe.
 """
 import concurrent.futures
 import glob
@@ -58,7 +59,26 @@ def build(verbose=True, lib=LIB, build_dir=BUILD, defines=()):
     os.replace(tmp, lib)
     if verbose:
         print(f"built {lib} from {len(sources)} sources", flush=True)
+    if lib == LIB:
+        build_probe(verbose)
     return lib
+
+
+PROBE_SRC = os.path.join(PKG, "probe", "issue_probe.hip")
+PROBE = os.path.join(PKG, "probe", "issue_probe")
+
+
+def build_probe(verbose=True):
+    """The issue-rate probe (probe/issue_probe.hip), a stand-alone program
+    that measures the throughput of single vector-ALU instruction classes."""
+    tmp = PROBE + ".tmp"
+    res = subprocess.run([HIPCC, *CFLAGS, PROBE_SRC, "-o", tmp], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, PROBE)
+    if verbose:
+        print(f"built {PROBE}", flush=True)
+    return PROBE
 
 
 def build_host_sanitized(build_dir=os.path.join(ROOT, "_build_san")):
