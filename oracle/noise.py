@@ -3,26 +3,22 @@
 The paper draws its Gaussian white noise from SPRNG without fixing how cells
 map to random numbers.  The reading used here: cell (m0, m1, m2), m_i in
 [0, N), has linear index c = (m0 N + m1) N + m2 (row-major, axis 2
-contiguous).  Four consecutive cells c = 4q + j (j = 0..3) share one
-Philox-4x32-10 call with
+contiguous) and is one Philox-4x32-10 call with
 
     key     = (seed mod 2^32, floor(seed / 2^32))
-    counter = (q mod 2^32, floor(q / 2^32), stream, 0).
+    counter = (c mod 2^32, floor(c / 2^32), stream, 0).
 
-Its words (w0, w1, w2, w3) form two Box-Muller pairs (``normal.py``, binary64):
-(w0, w1) gives cells 4q and 4q + 1, (w2, w3) cells 4q + 2 and 4q + 3; of a
-pair (wa, wb) the even cell takes r cos(2 pi u2) and the odd cell r sin(2 pi
-u2), with r = sqrt(-2 ln u1), u1 = (wa + 1) 2^-32, u2 = wb 2^-32.  The two
-deviates of a Box-Muller pair are independent unit Gaussians (Box and
-Muller 1958), and the two pairs come from independent words.  The
-single-precision field is each deviate rounded once to float32, so both
-precisions carry the same realisation.  ``stream`` separates independent
-fields drawn with the same seed.
+Of its words (w0, w1, w2, w3), w0 and w1 give the cell's deviate as the
+cosine branch of the Box-Muller transform of ``normal.py`` in binary64,
+g = sqrt(-2 ln u1) cos(2 pi u2), u1 = (w0 + 1) 2^-32, u2 = w1 2^-32; w2 and
+w3 are not used.  The single-precision field is g rounded once to float32,
+so both precisions carry the same realisation.  ``stream`` separates
+independent fields drawn with the same seed.
 """
 import numpy as np
 
 from .philox import philox4x32, seed_key
-from .normal import box_muller
+from .normal import gaussian
 
 
 def noise_cells(cells, seed, stream=0, dtype=np.float64):
@@ -30,13 +26,9 @@ def noise_cells(cells, seed, stream=0, dtype=np.float64):
     ``dtype`` (float64 or float32)."""
     cells = np.asarray(cells, dtype=np.uint64)
     key = seed_key(seed)
-    q = cells >> np.uint64(2)
-    j = cells & np.uint64(3)
-    w0, w1, w2, w3 = philox4x32(
-        (q & np.uint64(0xFFFFFFFF), q >> np.uint64(32), np.uint64(stream), np.uint64(0)), key)
-    second = j >= np.uint64(2)
-    g_cos, g_sin = box_muller(np.where(second, w2, w0), np.where(second, w3, w1))
-    return np.where((j & np.uint64(1)) == np.uint64(1), g_sin, g_cos).astype(dtype)
+    w0, w1, _, _ = philox4x32(
+        (cells & np.uint64(0xFFFFFFFF), cells >> np.uint64(32), np.uint64(stream), np.uint64(0)), key)
+    return gaussian(w0, w1).astype(dtype)
 
 
 def noise_grid(n, seed, stream=0, dtype=np.float64, chunk=1 << 22, workers=1):

@@ -12,8 +12,7 @@ in the order written below (no fused multiply-add).
 Box-Muller (G. E. P. Box and M. E. Muller, Ann. Math. Stat. 29 (1958) 610):
 from two uniforms u1 in (0, 1] and u2 in [0, 1),
     r = sqrt(-2 ln u1),  theta = 2 pi u2,  g_a = r cos theta,  g_b = r sin theta
-are two independent N(0,1) deviates; the noise field uses both (g_a for an
-even cell, g_b for the odd cell after it).
+are two independent N(0,1) deviates; the noise field keeps g_a only.
 
 Uniforms from two 32-bit words (w_a, w_b):
     u1 = (w_a + 1) * 2^-32  (exact; never 0, so ln is finite)
@@ -126,3 +125,7 @@ def box_muller(wa, wb):
     cos_t, sin_t = cos_sin_turn(wb)
     return r * cos_t, r * sin_t
 
+
+def gaussian(wa, wb):
+    """One N(0,1) deviate per word pair: the cosine branch r cos(2 pi u2)."""
+    return box_muller(wa, wb)[0]

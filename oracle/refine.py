@@ -17,7 +17,7 @@ with F = Eq. A.5-A.6 for N_L = 2 and F_0 = [1] for N_L = 1.
 New coefficients: the paper takes them from its generator; here the
 coefficient (i, j, k) of patch p (row-major over the patch grid) is the white
 noise value (oracle.noise) of index p N_H^3 + (i N_H + j) N_H + k in a given
-(seed, stream), as the noise cell of that index.
+(seed, stream): one Philox call per coefficient, like one cell of the noise.
 
 Combination (Eq. 4-5, r_s the cutoff scale, f(x) = [x < 1]):
     small scales: psi~_h(k) (1 - f(k r_s)) on the child grid;

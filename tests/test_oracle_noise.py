@@ -1,7 +1,6 @@
 """Pins for the oracle's white noise: elementary functions against the
 platform's extended-precision libm, Box-Muller against the normal law, and the
-cell-to-counter mapping (one Philox call per four cells: two Box-Muller pairs,
-cosine branch for the even cell of a pair, sine branch for the odd one)."""
+cell-to-counter mapping (one Philox call per cell, cosine branch)."""
 import numpy as np
 import pytest
 from scipy import stats
@@ -63,10 +62,9 @@ def test_noise_is_unit_gaussian():
     assert abs(w.var() - 1.0) < 5 * np.sqrt(2.0 / m)
     assert abs(stats.kurtosis(w, fisher=False) - 3.0) < 5 * np.sqrt(24.0 / m)
     assert stats.kstest(w, "norm").pvalue > 1e-3
-    # each of the four cells of a Philox call (cos / sin of either word pair)
-    # is N(0, 1) on its own
-    for lane in range(4):
-        assert stats.kstest(w[lane::4], "norm").pvalue > 1e-4
+    # even and odd cells (low counter bit) are each N(0, 1)
+    for lane in range(2):
+        assert stats.kstest(w[lane::2], "norm").pvalue > 1e-4
 
 
 def test_neighbouring_cells_uncorrelated():
@@ -77,48 +75,31 @@ def test_neighbouring_cells_uncorrelated():
 
 
 def test_cell_mapping():
-    # the noise of cell c = 4q + j only depends on (seed, stream, c): Philox
-    # call q with counter (q lo, q hi, stream, 0); words (w0, w1) for j < 2,
-    # (w2, w3) for j >= 2; r cos(theta) for even j, r sin(theta) for odd j.
-    # Checked against the Box-Muller formula in extended precision.
+    # the noise of cell c only depends on (seed, stream, c): one Philox call
+    # with counter (c lo, c hi, stream, 0), words w0 and w1, cosine branch
     seed = 123456789012345
-    cells = np.array([0, 1, 2, 3, 4, 7, 1 << 33, (1 << 33) + 1, (1 << 33) + 2, (1 << 33) + 3,
-                      (1 << 30) - 1, (1 << 34) + 6], dtype=np.uint64)
+    cells = np.array([0, 1, 2, 3, 4, 1 << 33, (1 << 33) + 3, (1 << 30) - 1], dtype=np.uint64)
     got = noise.noise_cells(cells, seed, stream=2)
     for c, g in zip(cells, got):
         c = int(c)
-        q, j = c >> 2, c & 3
         w = [int(np.asarray(x).reshape(-1)[0]) for x in philox.philox4x32(
-            (q & 0xFFFFFFFF, q >> 32, 2, 0), philox.seed_key(seed))]
-        wa, wb = (w[0], w[1]) if j < 2 else (w[2], w[3])
-        u1 = np.longdouble(wa + 1) * np.longdouble(2.0) ** -32
-        th = np.longdouble(wb) * np.longdouble(2.0) ** -32 * LD_TWO_PI
-        r = np.sqrt(-2 * np.log(u1))
-        want = r * (np.sin(th) if j & 1 else np.cos(th))
-        assert abs(g - float(want)) < 1e-14
-        # the other branch of the same pair is a different deviate
-        other = r * (np.cos(th) if j & 1 else np.sin(th))
-        assert abs(g - float(other)) > 1e-12
+            (c & 0xFFFFFFFF, c >> 32, 2, 0), philox.seed_key(seed))]
+        ga, _ = normal.box_muller(np.uint64(w[0]), np.uint64(w[1]))
+        assert g == float(ga)
+        # the deviate is r cos(theta) of the two words (extended precision)
+        u1 = np.longdouble(w[0] + 1) * np.longdouble(2.0) ** -32
+        th = np.longdouble(w[1]) * np.longdouble(2.0) ** -32 * LD_TWO_PI
+        assert abs(g - float(np.sqrt(-2 * np.log(u1)) * np.cos(th))) < 1e-14
 
 
-def test_pairs_share_radius_and_are_independent():
-    # g(4q)^2 + g(4q+1)^2 = -2 ln u1(w0) and g(4q+2)^2 + g(4q+3)^2 = -2 ln u1(w2)
-    # (cos^2 + sin^2 = 1); the two branches and the two pairs are uncorrelated
-    n = 1 << 18
-    cells = np.arange(n, dtype=np.uint64)
-    g = noise.noise_cells(cells, 77, stream=5).reshape(-1, 4)
-    q = np.arange(n // 4, dtype=np.uint64)
-    w0, _, w2, _ = philox.philox4x32((q, np.zeros_like(q), np.full_like(q, 5), np.zeros_like(q)),
-                                    philox.seed_key(77))
-    for a, wa in ((0, w0), (2, w2)):
-        r2 = -2.0 * np.log((wa + np.uint64(1)).astype(np.longdouble) * np.longdouble(2.0) ** -32)
-        s = g[:, a].astype(np.longdouble) ** 2 + g[:, a + 1].astype(np.longdouble) ** 2
-        assert float(np.max(np.abs(s - r2) / np.maximum(r2, 1e-30))) < 1e-14
-    lim = 5 / np.sqrt(g.shape[0])
-    for a, b in ((0, 1), (2, 3), (0, 2), (1, 3), (0, 3), (1, 2)):
-        assert abs(np.corrcoef(g[:, a], g[:, b])[0, 1]) < lim
-    # independent unit Gaussians: E[g_a^2 g_b^2] = 1 for the two branches of a pair
-    assert abs(np.mean(g[:, 0] ** 2 * g[:, 1] ** 2) - 1.0) < 0.05
+def test_gaussian_is_cosine_branch():
+    rng = np.random.default_rng(8)
+    wa = rng.integers(0, 1 << 32, 4096, dtype=np.uint64)
+    wb = rng.integers(0, 1 << 32, 4096, dtype=np.uint64)
+    ga, gb = normal.box_muller(wa, wb)
+    assert np.array_equal(normal.gaussian(wa, wb), ga)
+    # the sine branch is a different deviate: a mix-up of the branches would show
+    assert not np.allclose(ga, gb)
 
 
 def test_grid_chunking_and_precision():
