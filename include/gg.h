@@ -28,13 +28,11 @@
  *   The filter zeroes k = 0 and every mode with |s_j| = N/2 on any axis.
  * - Particle arrays: float32, structure of arrays, component j of cell c at
  *   j N^3 + c (3 N^3 values each for positions and velocities).
- * - Noise: cells c = 4q + j (j = 0..3) share one Philox-4x32-10 call
- *   (key = seed, counter = (q, stream_id, 0)); its words (w0, w1) and
- *   (w2, w3) are two Box-Muller pairs, sqrt(-2 ln u1) (cos, sin)(2 pi u2),
- *   the cosine for the even cell of a pair and the sine for the odd one,
- *   evaluated in binary64 with a fixed operation sequence, so a cell's value
- *   depends only on (seed, stream_id, c).  The float path stores that value
- *   rounded once.
+ * - Noise: cell c is one Philox-4x32-10 call (key = seed, counter =
+ *   (c, stream_id, 0)); its words w0, w1 give the cosine branch of the
+ *   Box-Muller transform, sqrt(-2 ln u1) cos(2 pi u2), evaluated in binary64
+ *   with a fixed operation sequence, so a cell's value depends only on
+ *   (seed, stream_id, c).  The float path stores that value rounded once.
  *
  * Memory, streams, errors
  * -----------------------

@@ -143,8 +143,7 @@ __device__ __forceinline__ int opaque(int x) {
 __device__ __forceinline__ int signed_mode(int k, int n) { return k < (n >> 1) ? k : k - n; }
 
 // ---------------------------------------------------------------------------
-// White noise, one Philox call (four consecutive cells) per thread and
-// iteration.  w is 16-byte aligned (the boundary asks for 256).
+// White noise, one cell per thread and iteration.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_noise(T* __restrict__ w, uint64_t ncells, uint64_t seed, uint32_t stream, const double2* lntab) {
@@ -155,23 +154,9 @@ __global__ void k_noise(T* __restrict__ w, uint64_t ncells, uint64_t seed, uint3
         __syncthreads();
         lnt = lt;
     }
-    const uint64_t nq = (ncells + 3) / 4;
-    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (uint64_t)gridDim.x * blockDim.x) {
-        T g[4];
-        noise_quad<T>(q, seed, stream, lnt, g);
-        const uint64_t c = 4 * q;
-        if (c + 4 <= ncells) {
-            if constexpr (std::is_same_v<T, float>) {
-                *reinterpret_cast<float4*>(w + c) = make_float4(g[0], g[1], g[2], g[3]);
-            } else {
-                reinterpret_cast<double2*>(w + c)[0] = make_double2(g[0], g[1]);
-                reinterpret_cast<double2*>(w + c)[1] = make_double2(g[2], g[3]);
-            }
-        } else {
-            for (int j = 0; j < 4; ++j)
-                if (c + j < ncells) w[c + j] = g[j];
-        }
-    }
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
+         c += (uint64_t)gridDim.x * blockDim.x)
+        w[c] = noise_value<T>(c, seed, stream, lnt);
 }
 
 // Lattice coordinates (m0, m1) of spectrum row r.  Plain rows are r = m0 N + m1;
@@ -260,7 +245,6 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
     const uint64_t line0 = row0 + (uint64_t)blockIdx.x * L;
 
     if constexpr (SRC == ZSRC_NOISE) {
-        static_assert(N % 4 == 0, "a Philox call covers four cells of a line");
         const double2* lnt = nullptr;
         if constexpr (std::is_same_v<T, float>) {
             __shared__ double2 lt[kLnTab];
@@ -268,18 +252,14 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
             __syncthreads();
             lnt = lt;
         }
-        // complex slot p of a line holds cells 2p, 2p+1, so one Philox call
-        // (cells 4h .. 4h+3) fills slots 2h and 2h+1; consecutive lanes take
-        // consecutive lines of the tile
-        for (int si = t; si < L * M / 2; si += NT) {
-            const int cc = si % L, h = si / L;
+        // complex slot p of a line holds cells 2p, 2p+1; sixteen lanes fill one
+        // slot row of the tile (sixteen lines)
+        for (int si = t; si < L * M; si += NT) {
+            const int cc = si % L, p = si / L;
             int m0, m1;
             row_coords<BLK>(line0 + cc, N, m0, m1);
-            const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 4 * h;
-            T g[4];
-            noise_quad<T>(cell >> 2, seed, stream, lnt, g);
-            lds[lidx<L>(2 * h, cc)] = {g[0], g[1]};
-            lds[lidx<L>(2 * h + 1, cc)] = {g[2], g[3]};
+            const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * p;
+            lds[lidx<L>(p, cc)] = {noise_value<T>(cell, seed, stream, lnt), noise_value<T>(cell + 1, seed, stream, lnt)};
         }
     } else {
         // four consecutive reals (two packed complex slots) per lane

@@ -1,15 +1,12 @@
-// Device white noise: one Philox-4x32-10 call per four cells -> two
-// Box-Muller pairs in binary64.
+// Device white noise: one Philox-4x32-10 call per cell -> one Box-Muller
+// deviate in binary64.
 //
 // The paper's step 1 (Sec. 2) asks for independent unit Gaussians per cell and
-// leaves the generator's mapping open.  Cells c = 4q + j (j = 0..3) share
-// Philox call q with key = the 64-bit seed and counter = (q low word, q high
-// word, stream, 0).  Its words (w0, w1) give cells 4q, 4q + 1 and (w2, w3)
-// cells 4q + 2, 4q + 3: a pair (wa, wb) gives r cos(2 pi u2) to the even cell
-// and r sin(2 pi u2) to the odd one, r = sqrt(-2 ln u1), u1 = (wa + 1) 2^-32,
-// u2 = wb 2^-32 (Box and Muller, Ann. Math. Stat. 29 (1958) 610: the two
-// values of a pair are independent unit Gaussians).  The float path stores
-// each value rounded once to float32.
+// leaves the generator's mapping open.  Cell c is one Philox call with key =
+// the 64-bit seed and counter = (c low word, c high word, stream, 0); of its
+// words, w0 and w1 give g = sqrt(-2 ln u1) cos(2 pi u2) (the cosine branch of
+// Box-Muller), u1 = (w0 + 1) 2^-32, u2 = w1 2^-32.  The float path stores g
+// rounded once to float32.
 //
 // Philox-4x32 (Salmon, Moraes, Dror, Shaw, SC'11): per round, the 64-bit
 // products M0*x0 and M1*x2 are split into high/low words and the state
@@ -21,11 +18,10 @@
 // binary64 implementation of the same sequence gives the same bits:
 //   ln u1 = e LN2 + 2 t P(t^2), u1 = m 2^e, m in [sqrt(1/2), sqrt(2)),
 //           t = (m-1)/(m+1), P = sum_{k<=11} t^(2k)/(2k+1) (Horner)
-//   cos and sin of 2 pi u2: quadrant from the top two bits, the 30-bit
-//           remainder reflected about pi/4 by an exact integer subtraction,
-//           then the Taylor series of cos (to x^16) and sin (to x^17) on
-//           [0, pi/4] (Horner in x^2), coefficients (-1)^k/(2k)! and
-//           (-1)^k/(2k+1)!; the quadrant only swaps and negates them.
+//   cos(2 pi u2): quadrant from the top two bits, the 30-bit remainder
+//           reflected about pi/4 by an exact integer subtraction, then the
+//           Taylor series of cos (to x^16) or sin (to x^17) on [0, pi/4]
+//           (Horner in x^2), coefficients (-1)^k/(2k)! and (-1)^k/(2k+1)!.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -99,12 +95,13 @@ __device__ __forceinline__ double bm_log(double u) {
     return a + b;
 }
 
-// cos and sin of 2 pi w 2^-32: with alpha = 2 pi rho 2^-32 the remainder
-// angle of the quadrant q, (cos, sin)(q pi/2 + alpha) is (ca, sa), (-sa, ca),
-// (-ca, -sa), (sa, -ca) for q = 0..3, where (ca, sa) = (cos alpha, sin alpha)
-// = (C(x), S(x)) when rho < 2^29 (x = alpha) and (S(x), C(x)) after
-// reflection (x = pi/2 - alpha).
-__device__ __forceinline__ void bm_cos_sin(uint32_t w, double& c, double& s) {
+// cos(2 pi w 2^-32): with alpha = 2 pi rho 2^-32 the remainder angle of the
+// quadrant q, cos(q pi/2 + alpha) is cos alpha, -sin alpha, -cos alpha,
+// sin alpha for q = 0..3; cos alpha = C(x), sin alpha = S(x) when rho < 2^29
+// (x = alpha), and the other way round after reflection (x = pi/2 - alpha).
+// Both series are evaluated (straight-line code, no per-term selects) and
+// the one the quadrant and reflection call for is kept.
+__device__ __forceinline__ double bm_cos(uint32_t w) {
 #pragma clang fp contract(off)
     const uint32_t q = w >> 30;
     const uint32_t rho = w & 0x3FFFFFFFu;
@@ -112,45 +109,33 @@ __device__ __forceinline__ void bm_cos_sin(uint32_t w, double& c, double& s) {
     const uint32_t n = direct ? rho : (1u << 30) - rho;
     const double x = ((double)n * kTwoM32) * kTwoPi;
     const double z = x * x;
+    const bool use_cos = ((q & 1u) == 0u) == direct;
     double pc = cos_coeff(kTrigTerms), ps = sin_coeff(kTrigTerms);
 #pragma unroll
     for (int k = kTrigTerms - 1; k >= 0; --k) {
         pc = pc * z + cos_coeff(k);
         ps = ps * z + sin_coeff(k);
     }
-    const double sx = x * ps;
-    const double ca = direct ? pc : sx, sa = direct ? sx : pc;
-    c = (q & 1u) ? sa : ca;
-    s = (q & 1u) ? ca : sa;
-    if (q == 1u || q == 2u) c = -c;
-    if (q >= 2u) s = -s;
+    const double v = use_cos ? pc : x * ps;
+    return (q == 1u || q == 2u) ? -v : v;
 }
 
-// The binary64 Box-Muller pair of the words wa, wb.
-__device__ __forceinline__ void gaussian_pair(uint32_t wa, uint32_t wb, double& gc, double& gs) {
+// The binary64 deviate of a cell from its words w0, w1.
+__device__ __forceinline__ double gaussian_words(uint32_t w0, uint32_t w1) {
 #pragma clang fp contract(off)
-    const double u1 = (double)((uint64_t)wa + 1ull) * kTwoM32;
+    const double u1 = (double)((uint64_t)w0 + 1ull) * kTwoM32;
     const double r = sqrt(-2.0 * bm_log(u1));
-    double c, s;
-    bm_cos_sin(wb, c, s);
-    gc = r * c;
-    gs = r * s;
+    return r * bm_cos(w1);
 }
 
-// The words of Philox call q (cells 4q .. 4q + 3).
-__device__ __forceinline__ u32x4 quad_words(uint64_t q, uint64_t seed, uint32_t stream) {
-    return philox4x32_10({(uint32_t)q, (uint32_t)(q >> 32), stream, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
+__device__ __forceinline__ u32x4 cell_words(uint64_t c, uint64_t seed, uint32_t stream) {
+    return philox4x32_10({(uint32_t)c, (uint32_t)(c >> 32), stream, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 // The binary64 deviate of cell c.
 __device__ __forceinline__ double gaussian_cell(uint64_t c, uint64_t seed, uint32_t stream) {
-    const u32x4 w = quad_words(c >> 2, seed, stream);
-    double gc, gs;
-    if (c & 2u)
-        gaussian_pair(w.z, w.w, gc, gs);
-    else
-        gaussian_pair(w.x, w.y, gc, gs);
-    return (c & 1u) ? gs : gc;
+    const u32x4 w = cell_words(c, seed, stream);
+    return gaussian_words(w.x, w.y);
 }
 
 // Logarithm table of the float path.  A positive double u is written
@@ -184,18 +169,18 @@ inline void make_ln_table(double2* t) {
     }
 }
 
-// The same pair to about 2^-46 relative, for the float path: -2 ln u1 from
-// the table above and ln(1 + r) to r^6 (truncation below 2^-50 of the
+// The same deviate to about 2^-46 relative, for the float path: -2 ln u1
+// from the table above and ln(1 + r) to r^6 (truncation below 2^-50 of the
 // result, also next to the bucket of 1), the square root by a reciprocal
-// square root estimate and one Goldschmidt step (the estimate is good to
-// about 2^-24, the step leaves about 2^-47), and cos and sin of the reflected
-// angle x in [0, pi/4] as above but in FMA form, cos to x^16 and sin to x^15
-// (truncation below 2^-53).  u1 is the exact value the defining sequence
-// forms; r = -0 when -2 ln u1 = 0, as sqrt(-0) gives there.  lnt: the
-// table, in LDS.
-__device__ __forceinline__ void gaussian_pair_fast(uint32_t wa, uint32_t wb, const double2* lnt, double& gc,
-                                                   double& gs) {
-    const double u1 = fma((double)wa, kTwoM32, kTwoM32);  // (wa + 1) 2^-32, exact
+// square root estimate and one Goldschmidt step, and cos(2 pi u2) as
+// +-sin(2 pi n 2^-32) with n in [0, 2^30] (cos(alpha) = sin(pi/2 - alpha)
+// taken on the integer angle, so one odd Taylor series to x^19 covers every
+// quadrant; truncation below 2^-51 on [0, pi/2]).  The hardware estimate is
+// good to about 2^-24, so the refinement leaves about 2^-47.  u1 is the exact
+// value the defining sequence forms; r = -0 when -2 ln u1 = 0, as sqrt(-0)
+// gives there.  lnt: the table, in LDS.
+__device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1, const double2* lnt) {
+    const double u1 = fma((double)w0, kTwoM32, kTwoM32);  // (w0 + 1) 2^-32, exact
     const uint64_t ix = (uint64_t)__double_as_longlong(u1);
     const uint64_t tb = ix - kLnTabLoBits;
     const int k = (int)((int64_t)tb >> 52);
@@ -212,62 +197,38 @@ __device__ __forceinline__ void gaussian_pair_fast(uint32_t wa, uint32_t wb, con
     const double g0 = a * y, h0 = 0.5 * y;
     const double rr = fma(-g0, h0, 0.5);
     const double r = a > 0.0 ? fma(g0, rr, g0) : -0.0;
-    const uint32_t q = wb >> 30;
-    const uint32_t rho = wb & 0x3FFFFFFFu;
-    const bool direct = rho < (1u << 29);
-    const uint32_t n = direct ? rho : (1u << 30) - rho;
+    const uint32_t q = w1 >> 30;
+    const uint32_t rho = w1 & 0x3FFFFFFFu;
+    const uint32_t n = (q & 1u) ? rho : (1u << 30) - rho;
     const double x = (double)n * (kTwoPi * kTwoM32);
     const double zz = x * x;
-    double pc = cos_coeff(8), ps = sin_coeff(7);
+    double ps = sin_coeff(9);
 #pragma unroll
-    for (int j = 7; j >= 0; --j) pc = fma(pc, zz, cos_coeff(j));
-#pragma unroll
-    for (int j = 6; j >= 0; --j) ps = fma(ps, zz, sin_coeff(j));
-    const double sx = x * ps;
-    // |cos theta| is C(x) when the reflection and the quadrant's swap cancel
-    const bool c_is_pc = direct == ((q & 1u) == 0u);
-    const double cm = c_is_pc ? pc : sx, sm = c_is_pc ? sx : pc;
-    gc = r * ((q == 1u || q == 2u) ? -cm : cm);
-    gs = r * (q >= 2u ? -sm : sm);
+    for (int j = 8; j >= 0; --j) ps = fma(ps, zz, sin_coeff(j));
+    const double v = x * ps;
+    return r * ((q == 1u || q == 2u) ? -v : v);
 }
 
-// Whether a binary64 value within 2^-42 |g| of g rounds to the same float as
+// Cell c's deviate in the path's type: binary64 as defined above, or that
+// value rounded once to float.  The float case rounds the fast evaluation g
+// when every value within 2^-42 |g| of it rounds to the same float, and
+// evaluates the defining sequence otherwise (about one cell in 10^5); the
+// exact deviate lies within 2^-46 |g| of g.  The test works on the bits of
 // g: a float rounding boundary of a normal double lies where its 29 low
-// mantissa bits read 2^28, and 2^-42 |g| is below 2^11 units in the last place
-// of g, so g is safe when those bits are more than 2^11 from 2^28 (|g| >
-// 2^-46 or g = 0 always, so float subnormals do not arise).
-__device__ __forceinline__ bool float_safe(double g) {
-    const uint32_t lo29 = (uint32_t)__double_as_longlong(g) & 0x1FFFFFFFu;
-    return lo29 - 0x10000000u + 2048u > 4096u;
-}
-
-// The four cells of Philox call q in the path's type: binary64 as defined
-// above, or those values rounded once to float.  The float case rounds the
-// fast pair when both its values pass float_safe (the exact values lie within
-// 2^-46 |g| of the fast ones) and evaluates the defining pair otherwise
-// (about one pair in 10^5).  lnt: the float path's logarithm table in LDS
-// (unused by the double path).
+// mantissa bits read 2^28, and 2^-42 |g| is below 2^11 units in the last
+// place of g, so g is safe when those bits are more than 2^11 from 2^28
+// (|g| > 2^-46 or g = 0 always, so float subnormals do not arise).
+// lnt: the float path's logarithm table in LDS (unused by the double path).
 template <typename T>
-__device__ __forceinline__ void noise_quad(uint64_t q, uint64_t seed, uint32_t stream, const double2* lnt, T* g) {
-    const u32x4 w = quad_words(q, seed, stream);
+__device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t stream, const double2* lnt) {
+    const u32x4 w = cell_words(c, seed, stream);
     if constexpr (std::is_same_v<T, float>) {
-        double a0, a1, b0, b1;
-        gaussian_pair_fast(w.x, w.y, lnt, a0, a1);
-        gaussian_pair_fast(w.z, w.w, lnt, b0, b1);
-        if (__builtin_expect(!(float_safe(a0) && float_safe(a1)), 0)) gaussian_pair(w.x, w.y, a0, a1);
-        if (__builtin_expect(!(float_safe(b0) && float_safe(b1)), 0)) gaussian_pair(w.z, w.w, b0, b1);
-        g[0] = (float)a0;
-        g[1] = (float)a1;
-        g[2] = (float)b0;
-        g[3] = (float)b1;
+        const double g = gaussian_words_fast(w.x, w.y, lnt);
+        const uint32_t lo29 = (uint32_t)__double_as_longlong(g) & 0x1FFFFFFFu;
+        if (__builtin_expect(lo29 - 0x10000000u + 2048u > 4096u, 1)) return (float)g;
+        return (float)gaussian_words(w.x, w.y);
     } else {
-        double a0, a1, b0, b1;
-        gaussian_pair(w.x, w.y, a0, a1);
-        gaussian_pair(w.z, w.w, b0, b1);
-        g[0] = a0;
-        g[1] = a1;
-        g[2] = b0;
-        g[3] = b1;
+        return gaussian_words(w.x, w.y);
     }
 }
 

@@ -128,8 +128,7 @@ hipError_t launch_xfilt(const StridedArgs<T>& a0, const PlanView<T>& pv, hipStre
 template <typename T>
 hipError_t Ops<T>::noise(const PlanView<T>& pv, uint64_t seed, uint32_t stream_id, T* w, hipStream_t s) {
     const uint64_t n3 = (uint64_t)pv.n * pv.n * pv.n;
-    if (((uintptr_t)w & 15u) != 0) return hipErrorInvalidValue;
-    k_noise<T><<<capped_grid((n3 + 3) / 4, 256), 256, 0, s>>>(w, n3, seed, stream_id, pv.lntab);
+    k_noise<T><<<capped_grid(n3, 256), 256, 0, s>>>(w, n3, seed, stream_id, pv.lntab);
     return hipGetLastError();
 }
 

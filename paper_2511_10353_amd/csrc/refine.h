@@ -8,7 +8,7 @@
 // unit Gaussian, and the child patch is sum a_ijk E_i E_j E_k (Eq. A.28).
 // The new coefficient (i, j, k) of patch p (row-major over the patch grid) is
 // the binary64 noise value of index p NH^3 + (i NH + j) NH + k for the given
-// seed and stream (the noise cell of that index).  One thread refines
+// seed and stream (one Philox call, as one noise cell).  One thread refines
 // one patch in binary64; the child values are rounded once to T.
 #pragma once
 #include <hip/hip_runtime.h>
