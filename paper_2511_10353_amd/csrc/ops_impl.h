@@ -42,10 +42,10 @@ struct ZLines {
 };
 
 // Lines per work-group of the first pass (noise + axis-2 transform): its LDS
-// tile is kept to GG_P1_LDS bytes so that a work-group of it fits on a compute
-// unit beside one of the axis-1 pass (128 KB of LDS at N = 1024), letting the
-// pipelined chunks of the two passes share compute units (noise arithmetic
-// alongside memory-bound transposes).
+// tile is kept to GG_P1_LDS bytes.  Sized so that a work-group of it would fit
+// on a compute unit beside one of the axis-1 pass (128 KB of LDS at N = 1024);
+// that sharing never paid when measured, and with the float path's 2 KB
+// logarithm table beside the tile the two no longer fit together.
 #ifndef GG_P1_LDS
 #define GG_P1_LDS 32768
 #endif
