@@ -138,14 +138,14 @@ __device__ __forceinline__ double gaussian_cell(uint64_t c, uint64_t seed, uint3
     return gaussian_words(w.x, w.y);
 }
 
-// Logarithm table of the float path.  A positive double u is written
-// u = 2^k z with z in [kLnTabLo, 2 kLnTabLo) (about [0.709, 1.418)) by
-// integer arithmetic on its bits: t = bits(u) - bits(kLnTabLo), k = t >> 52
-// (arithmetic), bits(z) = bits(u) - k 2^52.  Bits 45..51 of t select one of
+// Logarithm table of the float path.  With z0 the double whose bits are
+// kLnTabLoBits (about 0.709), a positive double u is written u = 2^k z with z
+// in [z0, 2 z0) by integer arithmetic on its bits: t = bits(u) - kLnTabLoBits,
+// k = t >> 52 (arithmetic), bits(z) = bits(u) - k 2^52.  Bits 45..51 of t select one of
 // 128 buckets of z, equal in bit space (2^-8 wide below 1, 2^-7 above).
 // Entry i is (invc, 2 ln invc) for an inverse centre invc of bucket i, so
 // that ln u = k ln 2 - ln invc + ln(1 + r) with r = z invc - 1, |r| < 2^-8.
-// kLnTabLo is placed so that 1 lies in the middle of its bucket, whose entry
+// z0 is placed so that 1 lies in the middle of its bucket, whose entry
 // is (1, 0): near u = 1 the logarithm is ln(1 + r) with r = z - 1 exact, and
 // next to that bucket |ln z| > 2^-9.5, so the cancellation of 2 ln invc
 // against 2 ln(1 + r) costs at most a factor of about 2.
