@@ -244,6 +244,7 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
     const int c = t % L, j = t / L;
     const uint64_t line0 = row0 + (uint64_t)blockIdx.x * L;
 
+    cx<T> v[V];
     if constexpr (SRC == ZSRC_NOISE) {
         const double2* lnt = nullptr;
         if constexpr (std::is_same_v<T, float>) {
@@ -252,14 +253,16 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
             __syncthreads();
             lnt = lt;
         }
-        // complex slot p of a line holds cells 2p, 2p+1; sixteen lanes fill one
-        // slot row of the tile (sixteen lines)
-        for (int si = t; si < L * M; si += NT) {
-            const int cc = si % L, p = si / L;
-            int m0, m1;
-            row_coords<BLK>(line0 + cc, N, m0, m1);
-            const uint64_t cell = ((uint64_t)m0 * N + m1) * N + 2 * p;
-            lds[lidx<L>(p, cc)] = {noise_value<T>(cell, seed, stream, lnt), noise_value<T>(cell + 1, seed, stream, lnt)};
+        // complex slot p of a line holds cells 2p, 2p+1; each thread draws the
+        // slots its first transform stage takes, so the tile is not staged
+        // through LDS
+        int m0, m1;
+        row_coords<BLK>(line0 + c, N, m0, m1);
+        const uint64_t base = ((uint64_t)m0 * N + m1) * N;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const uint64_t cell = base + 2 * (uint64_t)first_pos<M, -1>(j, i);
+            v[i] = {noise_value<T>(cell, seed, stream, lnt), noise_value<T>(cell + 1, seed, stream, lnt)};
         }
     } else {
         // four consecutive reals (two packed complex slots) per lane
@@ -307,12 +310,11 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
         if constexpr (SRC == ZSRC_GRAD) {
             if (zs.part) block_sum<NT>(dacc, zs.part + (uint64_t)blockIdx.y * gridDim.x + blockIdx.x);
         }
-    }
-    __syncthreads();
-    cx<T> v[V];
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = lds[lidx<L>(first_pos<M, -1>(j, i), c)];
-    __syncthreads();
+        for (int i = 0; i < V; ++i) v[i] = lds[lidx<L>(first_pos<M, -1>(j, i), c)];
+        __syncthreads();
+    }
     fft_lines<T, M, L, -1, 2>(v, lds, tw, c, j);
 #pragma unroll
     for (int i = 0; i < V; ++i) lds[lidx<L>(last_pos<M, -1>(j, i), c)] = v[i];
