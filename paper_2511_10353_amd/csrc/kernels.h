@@ -256,13 +256,14 @@ __global__ __launch_bounds__(L * PlanInfo<N / 2>::TPL) void k_zfwd(ZSrc<T> zs, c
         // complex slot p of a line holds cells 2p, 2p+1; each thread draws the
         // slots its first transform stage takes, so the tile is not staged
         // through LDS
+        static_assert((uint64_t)N * N * N <= (1ull << 32), "cell indices are 32-bit");
         int m0, m1;
         row_coords<BLK>(line0 + c, N, m0, m1);
-        const uint64_t base = ((uint64_t)m0 * N + m1) * N;
+        const uint32_t base = ((uint32_t)m0 * N + (uint32_t)m1) * N;
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-            const uint64_t cell = base + 2 * (uint64_t)first_pos<M, -1>(j, i);
-            v[i] = {noise_value<T>(cell, seed, stream, lnt), noise_value<T>(cell + 1, seed, stream, lnt)};
+            const uint32_t cell = base + 2u * (uint32_t)first_pos<M, -1>(j, i);
+            v[i] = {noise_value32<T>(cell, seed, stream, lnt), noise_value32<T>(cell + 1, seed, stream, lnt)};
         }
     } else {
         // four consecutive reals (two packed complex slots) per lane

@@ -41,9 +41,10 @@ struct u32x4 {
     uint32_t x, y, z, w;
 };
 
-__device__ __forceinline__ u32x4 philox4x32_10(u32x4 ctr, uint32_t k0, uint32_t k1) {
+template <int ROUNDS>
+__device__ __forceinline__ u32x4 philox_rounds(u32x4 ctr, uint32_t k0, uint32_t k1) {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         // one 32x32 -> 64-bit product per multiplier gives both halves; the
         // three-input XORs are single v_bitop3 instructions (truth table 0x96)
         const uint64_t p0 = (uint64_t)kPhiloxM0 * ctr.x;
@@ -56,6 +57,29 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 ctr, uint32_t k0, uint32_t 
         k1 += kPhiloxW1;
     }
     return ctr;
+}
+
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 ctr, uint32_t k0, uint32_t k1) {
+    return philox_rounds<10>(ctr, k0, k1);
+}
+
+// Philox-4x32-10 of the counter (c, 0, stream, 0), the same function with its
+// first two rounds written out: the words that depend only on the key and the
+// stream (the first after round one, the last after round two) and the
+// product between them stay wave-uniform, in scalar registers.
+__device__ __forceinline__ u32x4 philox4x32_10_c32(uint32_t c, uint32_t stream, uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * stream;
+    const uint32_t x0 = (uint32_t)(p1 >> 32) ^ k0;  // the counter's words 1 and 3 are 0
+    const uint32_t x1 = (uint32_t)p1;
+    const uint32_t x2 = (uint32_t)(p0 >> 32) ^ k1;
+    const uint32_t x3 = (uint32_t)p0;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    const uint64_t q0 = (uint64_t)kPhiloxM0 * x0;
+    const uint64_t q1 = (uint64_t)kPhiloxM1 * x2;
+    const u32x4 ctr = {(uint32_t)(q1 >> 32) ^ x1 ^ k0, (uint32_t)q1, (uint32_t)(q0 >> 32) ^ x3 ^ k1, (uint32_t)q0};
+    return philox_rounds<8>(ctr, k0 + kPhiloxW0, k1 + kPhiloxW1);
 }
 
 constexpr double kLn2 = 0.6931471805599453;
@@ -220,8 +244,7 @@ __device__ __forceinline__ double gaussian_words_fast(uint32_t w0, uint32_t w1, 
 // (|g| > 2^-46 or g = 0 always, so float subnormals do not arise).
 // lnt: the float path's logarithm table in LDS (unused by the double path).
 template <typename T>
-__device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t stream, const double2* lnt) {
-    const u32x4 w = cell_words(c, seed, stream);
+__device__ __forceinline__ T noise_of_words(const u32x4& w, const double2* lnt) {
     if constexpr (std::is_same_v<T, float>) {
         const double g = gaussian_words_fast(w.x, w.y, lnt);
         const uint32_t lo29 = (uint32_t)__double_as_longlong(g) & 0x1FFFFFFFu;
@@ -230,6 +253,19 @@ __device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t str
     } else {
         return gaussian_words(w.x, w.y);
     }
+}
+
+template <typename T>
+__device__ __forceinline__ T noise_value(uint64_t c, uint64_t seed, uint32_t stream, const double2* lnt) {
+    return noise_of_words<T>(cell_words(c, seed, stream), lnt);
+}
+
+// The same for a cell index below 2^32 (every lattice here has at most 2^30
+// cells): the counter's high word is 0, so part of the first two rounds
+// depends only on the seed and the stream (philox4x32_10_c32).
+template <typename T>
+__device__ __forceinline__ T noise_value32(uint32_t c, uint64_t seed, uint32_t stream, const double2* lnt) {
+    return noise_of_words<T>(philox4x32_10_c32(c, stream, (uint32_t)seed, (uint32_t)(seed >> 32)), lnt);
 }
 
 }  // namespace gg
